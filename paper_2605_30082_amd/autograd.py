@@ -1,0 +1,61 @@
+"""Differentiable pressure-Poisson solve.
+
+Forward: p = zero-mean solution of L(beta) p = rhs - mean(rhs).
+Backward, for an upstream gradient w = dLoss/dp:
+  lambda = zero-mean solution of L lambda = w - mean(w)   (L is symmetric, so the
+           adjoint solve reuses the forward hierarchy),
+  dLoss/drhs    = lambda,
+  dLoss/dbeta_f = (lambda_R - lambda_L)(p_R - p_L) / h^2 on interior faces
+                  (one fused face-gradient kernel), 0 on walls.
+p is recomputed in the backward pass from the saved (rhs, beta) unless
+save_p=True; no V-cycle state is stored.
+"""
+from __future__ import annotations
+
+import torch
+
+from .solver import Solver
+
+
+class PoissonSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rhs, beta_x, beta_y, beta_z, h, tol, precision, save_p):
+        solver = Solver(beta_x, beta_y, beta_z, h, precision=precision, zero_guess=True)
+        p, _ = solver.solve(rhs.contiguous(), tol)
+        ctx.h, ctx.tol, ctx.precision, ctx.save_p = float(h), float(tol), precision, bool(save_p)
+        ctx.solver = solver
+        if save_p:
+            ctx.save_for_backward(rhs, beta_x, beta_y, beta_z, p)
+        else:
+            ctx.save_for_backward(rhs, beta_x, beta_y, beta_z)
+        return p
+
+    @staticmethod
+    def backward(ctx, grad_p):
+        saved = ctx.saved_tensors
+        rhs, bx, by, bz = saved[:4]
+        solver = ctx.solver
+        need_rhs, need_bx, need_by, need_bz = ctx.needs_input_grad[:4]
+        g_rhs = g_x = g_y = g_z = None
+        if need_rhs or need_bx or need_by or need_bz:
+            lam, _ = solver.solve_adjoint(grad_p.contiguous(), ctx.tol)
+            if need_rhs:
+                g_rhs = lam
+            if need_bx or need_by or need_bz:
+                if ctx.save_p:
+                    p = saved[4]
+                else:
+                    p, _ = solver.solve(rhs.contiguous(), ctx.tol)
+                gx, gy, gz = solver.face_grad(lam, p)
+                g_x = gx if need_bx else None
+                g_y = gy if need_by else None
+                g_z = gz if need_bz else None
+        solver.close()
+        ctx.solver = None
+        return g_rhs, g_x, g_y, g_z, None, None, None, None
+
+
+def poisson_solve(rhs, beta_x, beta_y, beta_z, h, tol: float = 1e-10, precision: str = "fp64",
+                  save_p: bool = False):
+    """Differentiable zero-mean solve of div(beta grad p) = rhs - mean(rhs)."""
+    return PoissonSolve.apply(rhs, beta_x, beta_y, beta_z, h, tol, precision, save_p)

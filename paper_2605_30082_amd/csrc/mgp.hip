@@ -1,0 +1,914 @@
+// Host side of the MI355X multigrid pressure-Poisson solver: level hierarchy,
+// V-cycle driver, FP64 defect-correction loop, adjoint, C ABI (include/mgp.h).
+#include "mgp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "mgp_kernels.hpp"
+#include "mgp_sweep.hpp"
+
+using namespace mgp;
+
+namespace {
+
+constexpr int kMaxCoarseCells = 64;
+constexpr int kTimingPairs = 4096;
+
+template <typename T>
+struct LevelBufs {
+    T *bx = nullptr, *by = nullptr, *bz = nullptr;  // low-face coefficients
+    T *x = nullptr, *t = nullptr, *b = nullptr;     // iterate, ping-pong partner, rhs
+};
+
+struct Level {
+    Dims d{};
+    long n = 0;
+    double h = 0.0;
+    LevelBufs<double> f64;
+    LevelBufs<float> f32;
+};
+
+}  // namespace
+
+struct mg_ctx {
+    int nlev = 0;
+    Level lev[MG_MAX_LEVELS];
+    mg_opts opts{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool mixed = false;
+    double* G = nullptr;         // coarsest inverse, n_c x n_c
+    double* b0 = nullptr;        // projected rhs, finest
+    double* ptmp = nullptr;      // ping-pong partner of the caller's p
+    double* work = nullptr;      // scratch (coarse inverse build; verification copies)
+    double* partials = nullptr;  // kReduceBlocks
+    double* scal = nullptr;      // device scalars
+    double* host_scal = nullptr; // pinned host mirror
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    double setup_ms = 0.0;
+    bool valid = false;          // coefficients imported and accepted
+    // timing
+    hipEvent_t* ev = nullptr;
+    int ev_class[kTimingPairs];
+    double ev_bytes[kTimingPairs];
+    int ev_used = 0;
+    double kms[MG_K_COUNT];
+    long long klaunch[MG_K_COUNT];
+    double kbytes[MG_K_COUNT];
+    char err[512];
+};
+
+namespace {
+
+thread_local char g_setup_err[512] = "";
+
+void set_err(mg_ctx* c, const char* fmt, ...)
+{
+    if (!c) return;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+}
+
+#define HIP_TRY(ctx, call)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            set_err((ctx), "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                    __LINE__);                                                              \
+            return MG_EHIP;                                                                 \
+        }                                                                                   \
+    } while (0)
+
+#define CHECK_LAUNCH(ctx) HIP_TRY(ctx, hipGetLastError())
+
+int grid_for(long n)
+{
+    long g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > kReduceBlocks) g = kReduceBlocks;
+    return (int)g;
+}
+
+// plan: number of levels; 0 if invalid
+int plan(int nx, int ny, int nz, int coarse_max, Dims* out)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || coarse_max < 1) return 0;
+    if ((long)nx * ny * nz >= (1L << 31)) return 0;
+    int n = 0;
+    for (;;) {
+        if (n >= MG_MAX_LEVELS) return 0;
+        if (out) out[n] = Dims{nx, ny, nz};
+        ++n;
+        if (nx <= coarse_max && ny <= coarse_max && nz <= coarse_max) break;
+        if ((nx & 1) || (ny & 1) || (nz & 1)) return 0;
+        nx /= 2;
+        ny /= 2;
+        nz /= 2;
+    }
+    return n;
+}
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// --- timing ---------------------------------------------------------------
+
+struct TimedLaunch {
+    mg_ctx* c;
+    int cls;
+    bool on;
+    TimedLaunch(mg_ctx* ctx, int level, int k, double bytes) : c(ctx), cls(k), on(false)
+    {
+        if (!c->ev || level != 0 || c->ev_used >= kTimingPairs) return;
+        on = true;
+        c->ev_class[c->ev_used] = k;
+        c->ev_bytes[c->ev_used] = bytes;
+        (void)hipEventRecord(c->ev[2 * c->ev_used], c->stream);
+    }
+    ~TimedLaunch()
+    {
+        if (!on) return;
+        (void)hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream);
+        c->ev_used++;
+    }
+};
+
+// after a stream synchronisation: fold recorded event pairs into the totals
+void harvest(mg_ctx* c)
+{
+    for (int t = 0; t < c->ev_used; ++t) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[2 * t], c->ev[2 * t + 1]) == hipSuccess) {
+            c->kms[c->ev_class[t]] += ms;
+            c->klaunch[c->ev_class[t]] += 1;
+            c->kbytes[c->ev_class[t]] += c->ev_bytes[t];
+        }
+    }
+    c->ev_used = 0;
+}
+
+// --- reductions -----------------------------------------------------------
+
+int reduce_to(mg_ctx* c, int nparts, int slot)
+{
+    k_reduce_final<<<1, kBlock, 0, c->stream>>>(c->partials, nparts, c->scal, slot);
+    CHECK_LAUNCH(c);
+    return MG_OK;
+}
+
+int fetch_scalars(mg_ctx* c, int count)
+{
+    HIP_TRY(c, hipMemcpyAsync(c->host_scal, c->scal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    harvest(c);
+    return MG_OK;
+}
+
+// --- level kernels ----------------------------------------------------------
+
+template <typename T>
+LevelBufs<T>& bufs(Level& L);
+template <>
+LevelBufs<double>& bufs<double>(Level& L) { return L.f64; }
+template <>
+LevelBufs<float>& bufs<float>(Level& L) { return L.f32; }
+
+template <typename T>
+int sweep(mg_ctx* c, int l, const T* b, const T* in, T* out, int order, bool zero_in)
+{
+    Level& L = c->lev[l];
+    LevelBufs<T>& B = bufs<T>(L);
+    const double bytes = (double)L.n * sweep_bytes_per_cell<T>();
+    TimedLaunch tl(c, l, MG_K_SWEEP, bytes);
+    const hipError_t e = launch_sweep<T>(B.bx, B.by, B.bz, L.d, (T)(L.h * L.h), b, in, out, order,
+                                         zero_in, c->stream);
+    if (e != hipSuccess) {
+        set_err(c, "sweep launch failed: %s", hipGetErrorString(e));
+        return MG_EHIP;
+    }
+    return MG_OK;
+}
+
+template <typename T>
+int residual_restrict(mg_ctx* c, int l, const T* b, const T* x, T* bc)
+{
+    Level& L = c->lev[l];
+    Level& C = c->lev[l + 1];
+    LevelBufs<T>& B = bufs<T>(L);
+    TimedLaunch tl(c, l, MG_K_RESTRICT, (double)L.n * (5.0 + 1.0 / 8.0) * sizeof(T));
+    k_residual_restrict<T><<<grid_for(C.n), kBlock, 0, c->stream>>>(B.bx, B.by, B.bz, L.d, C.d,
+                                                                   (T)(1.0 / (L.h * L.h)), b, x, bc);
+    CHECK_LAUNCH(c);
+    return MG_OK;
+}
+
+template <typename T>
+int prolong_correct(mg_ctx* c, int l, const T* e, T* x)
+{
+    Level& L = c->lev[l];
+    Level& C = c->lev[l + 1];
+    TimedLaunch tl(c, l, MG_K_PROLONG, (double)L.n * (2.0 + 1.0 / 8.0) * sizeof(T));
+    k_prolong_correct<T><<<grid_for(L.n), kBlock, 0, c->stream>>>(L.d, C.d, e, x);
+    CHECK_LAUNCH(c);
+    return MG_OK;
+}
+
+template <typename T>
+int coarse_apply(mg_ctx* c, const T* r, T* e)
+{
+    Level& L = c->lev[c->nlev - 1];
+    k_coarse_apply<T><<<1, 64, 0, c->stream>>>(c->G, (int)L.n, r, e);
+    CHECK_LAUNCH(c);
+    return MG_OK;
+}
+
+template <typename T>
+int fill(mg_ctx* c, T* x, long n, T v)
+{
+    k_fill<T><<<grid_for(n), kBlock, 0, c->stream>>>(x, n, v);
+    CHECK_LAUNCH(c);
+    return MG_OK;
+}
+
+#define TRY(...)                    \
+    do {                            \
+        int s_ = (__VA_ARGS__);     \
+        if (s_ != MG_OK) return s_; \
+    } while (0)
+
+// One V-cycle on level l.  *x holds the iterate (zero_init: treat as 0),
+// *t is its ping-pong partner; on return *x holds the result (the two
+// pointers may have been swapped).
+template <typename T>
+int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init)
+{
+    Level& L = c->lev[l];
+    if (l == c->nlev - 1) return coarse_apply<T>(c, b, *x);
+    const int pre = c->opts.pre, post = c->opts.post;
+    if (zero_init && pre == 0) TRY(fill<T>(c, *x, L.n, (T)0));
+    for (int s = 0; s < pre; ++s) {
+        TRY(sweep<T>(c, l, b, *x, *t, 0, zero_init && s == 0));
+        std::swap(*x, *t);
+    }
+    Level& C = c->lev[l + 1];
+    LevelBufs<T>& CB = bufs<T>(C);
+    TRY(residual_restrict<T>(c, l, b, *x, CB.b));
+    T* cx = CB.x;
+    T* ct = CB.t;
+    TRY(vcycle<T>(c, l + 1, &cx, &ct, CB.b, true));
+    TRY(prolong_correct<T>(c, l, cx, *x));
+    for (int s = 0; s < post; ++s) {
+        TRY(sweep<T>(c, l, b, *x, *t, 1, false));
+        std::swap(*x, *t);
+    }
+    return MG_OK;
+}
+
+int residual_norm_launch(mg_ctx* c, const double* b, const double* p, double* r_out, int slot)
+{
+    Level& L = c->lev[0];
+    TimedLaunch tl(c, 0, MG_K_NORM, (double)L.n * 5.0 * sizeof(double));
+    k_residual_norm<<<kReduceBlocks, kBlock, 0, c->stream>>>(L.f64.bx, L.f64.by, L.f64.bz, L.d,
+                                                             1.0 / (L.h * L.h), b, p, r_out, c->partials);
+    CHECK_LAUNCH(c);
+    return reduce_to(c, kReduceBlocks, slot);
+}
+
+// ---------------------------------------------------------------------------
+// solve driver shared by mg_solve and mg_solve_adjoint
+// ---------------------------------------------------------------------------
+
+int check_ctx(mg_ctx* c)
+{
+    if (!c) return MG_EINVAL;
+    HIP_TRY(c, hipSetDevice(c->device));
+    return MG_OK;
+}
+
+int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st)
+{
+    const double t0 = now_ms();
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->setup_ms = c->setup_ms;
+    }
+    if (!c->valid) {
+        set_err(c, "the context holds rejected face coefficients: call mg_update first");
+        return MG_EINVAL;
+    }
+    if (!rhs || !p || rhs == p) {
+        set_err(c, "rhs and p must be distinct non-NULL device pointers");
+        return MG_EINVAL;
+    }
+    if (!(tol > 0.0) || !std::isfinite(tol)) {
+        set_err(c, "tol must be finite and > 0 (got %g)", tol);
+        return MG_EINVAL;
+    }
+    for (int k = 0; k < MG_K_COUNT; ++k) {
+        c->kms[k] = 0;
+        c->klaunch[k] = 0;
+        c->kbytes[k] = 0;
+    }
+    c->ev_used = 0;
+    Level& F = c->lev[0];
+    const long n = F.n;
+    const bool zero_guess = (c->opts.flags & MG_FLAG_ZERO_GUESS) != 0;
+
+    // b0 = rhs - mean(rhs); ||b0||^2
+    k_sum<double><<<kReduceBlocks, kBlock, 0, c->stream>>>(rhs, n, c->partials);
+    CHECK_LAUNCH(c);
+    TRY(reduce_to(c, kReduceBlocks, 0));
+    k_sub_scalar_norm<<<kReduceBlocks, kBlock, 0, c->stream>>>(rhs, n, c->scal, 0, 1.0 / (double)n, c->b0,
+                                                               c->partials);
+    CHECK_LAUNCH(c);
+    TRY(reduce_to(c, kReduceBlocks, 1));
+    TRY(fetch_scalars(c, 2));
+    const double mu = c->host_scal[0] / (double)n;
+    const double bnorm = std::sqrt(c->host_scal[1]);
+    if (st) st->rhs_mean_removed = mu;
+    if (!std::isfinite(bnorm) || !std::isfinite(mu)) {
+        set_err(c, "right-hand side holds NaN or Inf");
+        if (st) st->status = MG_ENONFINITE;
+        return MG_ENONFINITE;
+    }
+    if (bnorm == 0.0) {
+        TRY(fill<double>(c, p, n, 0.0));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (st) {
+            st->solve_ms = now_ms() - t0;
+            st->status = MG_OK;
+        }
+        return MG_OK;
+    }
+
+    const int maxc = c->opts.max_cycles;
+    double rr = 1.0, best = 1.0;
+    int cycles = 0, status = MG_ENOCONV;
+    double* cur = p;        // buffer holding the current iterate
+    double* other = c->ptmp;
+
+    if (!c->mixed) {
+        if (zero_guess) {
+            rr = 1.0;
+        } else {
+            TRY(residual_norm_launch(c, c->b0, cur, nullptr, 2));
+            TRY(fetch_scalars(c, 3));
+            rr = std::sqrt(c->host_scal[2]) / bnorm;
+        }
+        if (st) st->hist[0] = rr;
+        best = rr;
+        if (!std::isfinite(rr)) status = MG_ENONFINITE;
+        else if (rr <= tol) status = MG_OK;
+        bool first = zero_guess;
+        while (status == MG_ENOCONV && cycles < maxc) {
+            TRY(vcycle<double>(c, 0, &cur, &other, c->b0, first));
+            first = false;
+            ++cycles;
+            TRY(residual_norm_launch(c, c->b0, cur, nullptr, 2));
+            TRY(fetch_scalars(c, 3));
+            rr = std::sqrt(c->host_scal[2]) / bnorm;
+            if (st && cycles < MG_HIST_MAX) st->hist[cycles] = rr;
+            if (!std::isfinite(rr)) { status = MG_ENONFINITE; break; }
+            if (rr <= tol) { status = MG_OK; break; }
+            best = std::min(best, rr);
+            if (rr > 1e3 * best) break;
+        }
+    } else {
+        Level& F0 = c->lev[0];
+        float* r32 = F0.f32.b;
+        // initial residual in FP64, cast to FP32
+        if (zero_guess) TRY(fill<double>(c, cur, n, 0.0));
+        {
+            TimedLaunch tl(c, 0, MG_K_OUTER, (double)n * (6 * 8 + 4 + 8));
+            k_outer_update<<<kReduceBlocks, kBlock, 0, c->stream>>>(F0.f64.bx, F0.f64.by, F0.f64.bz, F0.d,
+                                                                    1.0 / (F0.h * F0.h), c->b0, cur, nullptr, 1,
+                                                                    other, r32, c->partials);
+            CHECK_LAUNCH(c);
+        }
+        std::swap(cur, other);
+        TRY(reduce_to(c, kReduceBlocks, 2));
+        TRY(fetch_scalars(c, 3));
+        rr = std::sqrt(c->host_scal[2]) / bnorm;
+        if (st) st->hist[0] = rr;
+        best = rr;
+        if (!std::isfinite(rr)) status = MG_ENONFINITE;
+        else if (rr <= tol) status = MG_OK;
+        while (status == MG_ENOCONV && cycles < maxc) {
+            float* ex = F0.f32.x;
+            float* et = F0.f32.t;
+            TRY(vcycle<float>(c, 0, &ex, &et, r32, true));
+            {
+                TimedLaunch tl(c, 0, MG_K_OUTER, (double)n * (6 * 8 + 4 + 8 + 4));
+                k_outer_update<<<kReduceBlocks, kBlock, 0, c->stream>>>(F0.f64.bx, F0.f64.by, F0.f64.bz, F0.d,
+                                                                        1.0 / (F0.h * F0.h), c->b0, cur, ex, 0,
+                                                                        other, r32, c->partials);
+                CHECK_LAUNCH(c);
+            }
+            std::swap(cur, other);
+            TRY(reduce_to(c, kReduceBlocks, 2));
+            ++cycles;
+            TRY(fetch_scalars(c, 3));
+            rr = std::sqrt(c->host_scal[2]) / bnorm;
+            if (st && cycles < MG_HIST_MAX) st->hist[cycles] = rr;
+            if (!std::isfinite(rr)) { status = MG_ENONFINITE; break; }
+            if (rr <= tol) { status = MG_OK; break; }
+            best = std::min(best, rr);
+            if (rr > 1e3 * best) break;
+        }
+    }
+
+    // zero-mean result in the caller's buffer
+    k_sum<double><<<kReduceBlocks, kBlock, 0, c->stream>>>(cur, n, c->partials);
+    CHECK_LAUNCH(c);
+    TRY(reduce_to(c, kReduceBlocks, 3));
+    if (cur != p) HIP_TRY(c, hipMemcpyAsync(p, cur, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    k_sub_scalar<<<grid_for(n), kBlock, 0, c->stream>>>(p, n, c->scal, 3, 1.0 / (double)n);
+    CHECK_LAUNCH(c);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    harvest(c);
+
+    if (status == MG_ENOCONV) set_err(c, "no convergence after %d cycles (rel. residual %.3e)", cycles, rr);
+    if (status == MG_ENONFINITE) set_err(c, "non-finite residual norm after %d cycles", cycles);
+    if (st) {
+        st->cycles = cycles;
+        st->status = status;
+        st->rel_res = rr;
+        st->solve_ms = now_ms() - t0;
+        for (int k = 0; k < MG_K_COUNT; ++k) {
+            st->kernel_ms[k] = c->kms[k];
+            st->kernel_launches[k] = c->klaunch[k];
+            st->kernel_bytes[k] = c->kbytes[k];
+        }
+    }
+    return status;
+}
+
+void free_ctx(mg_ctx* c)
+{
+    if (!c) return;
+    if (c->ev) {
+        for (int t = 0; t < 2 * kTimingPairs; ++t)
+            if (c->ev[t]) (void)hipEventDestroy(c->ev[t]);
+        delete[] c->ev;
+    }
+    if (c->arena) (void)hipFree(c->arena);
+    if (c->host_scal) (void)hipHostFree(c->host_scal);
+    delete c;
+}
+
+// bump allocator over one device arena
+struct Arena {
+    char* base;
+    size_t off;
+    size_t cap;
+    template <typename T>
+    T* take(long count)
+    {
+        const size_t bytes = ((size_t)count * sizeof(T) + 255) & ~(size_t)255;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+void carve(mg_ctx* c, Arena& a)
+{
+    const long n0 = c->lev[0].n;
+    c->b0 = a.take<double>(n0);
+    c->ptmp = a.take<double>(n0);
+    const long nc = c->lev[c->nlev - 1].n;
+    c->G = a.take<double>(nc * nc);
+    const long m = nc + 1;
+    c->work = a.take<double>(std::max<long>(m * 2 * m, n0));
+    c->partials = a.take<double>(kReduceBlocks);
+    c->scal = a.take<double>(16);
+    for (int l = 0; l < c->nlev; ++l) {
+        Level& L = c->lev[l];
+        L.f64.bx = a.take<double>(L.n);
+        L.f64.by = a.take<double>(L.n);
+        L.f64.bz = a.take<double>(L.n);
+        L.f64.x = a.take<double>(L.n);
+        L.f64.t = a.take<double>(L.n);
+        L.f64.b = a.take<double>(L.n);
+        if (c->mixed) {
+            L.f32.bx = a.take<float>(L.n);
+            L.f32.by = a.take<float>(L.n);
+            L.f32.bz = a.take<float>(L.n);
+            L.f32.x = a.take<float>(L.n);
+            L.f32.t = a.take<float>(L.n);
+            L.f32.b = a.take<float>(L.n);
+        }
+    }
+}
+
+int setup_impl(mg_ctx* c, const double* pbx, const double* pby, const double* pbz)
+{
+    Level& F = c->lev[0];
+    k_import_faces<<<kReduceBlocks, kBlock, 0, c->stream>>>(pbx, pby, pbz, F.d, F.f64.bx, F.f64.by, F.f64.bz,
+                                                            c->partials);
+    CHECK_LAUNCH(c);
+    TRY(reduce_to(c, kReduceBlocks, 4));
+    for (int l = 1; l < c->nlev; ++l) {
+        Level& A = c->lev[l - 1];
+        Level& B = c->lev[l];
+        k_coarsen_faces<<<grid_for(B.n), kBlock, 0, c->stream>>>(A.f64.bx, A.f64.by, A.f64.bz, A.d, B.d,
+                                                                 B.f64.bx, B.f64.by, B.f64.bz);
+        CHECK_LAUNCH(c);
+    }
+    if (c->mixed) {
+        for (int l = 0; l < c->nlev; ++l) {
+            Level& L = c->lev[l];
+            k_convert<double, float><<<grid_for(L.n), kBlock, 0, c->stream>>>(L.f64.bx, L.n, L.f32.bx);
+            k_convert<double, float><<<grid_for(L.n), kBlock, 0, c->stream>>>(L.f64.by, L.n, L.f32.by);
+            k_convert<double, float><<<grid_for(L.n), kBlock, 0, c->stream>>>(L.f64.bz, L.n, L.f32.bz);
+            CHECK_LAUNCH(c);
+        }
+    }
+    Level& Cl = c->lev[c->nlev - 1];
+    k_coarse_inverse<<<1, kBlock, 0, c->stream>>>(Cl.f64.bx, Cl.f64.by, Cl.f64.bz, Cl.d, Cl.h, c->work, c->G,
+                                                  c->scal + 5);
+    CHECK_LAUNCH(c);
+    TRY(fetch_scalars(c, 6));
+    if (c->host_scal[4] != 0.0) {
+        set_err(c, "%.0f interior face coefficient(s) are not finite and > 0", c->host_scal[4]);
+        return MG_EINVAL;
+    }
+    if (c->host_scal[5] != 0.0) {
+        set_err(c, "coarsest-grid bordered matrix is singular");
+        return MG_EINVAL;
+    }
+    return MG_OK;
+}
+
+mg_ctx* as_ctx(const mg_ctx* c) { return const_cast<mg_ctx*>(c); }
+
+int level_ok(mg_ctx* c, int level, int precision)
+{
+    if (level < 0 || level >= c->nlev) {
+        set_err(c, "level %d out of range [0, %d)", level, c->nlev);
+        return MG_EINVAL;
+    }
+    if (precision != MG_PREC_FP64 && precision != MG_PREC_MIXED) {
+        set_err(c, "precision must be MG_PREC_FP64 or MG_PREC_MIXED");
+        return MG_EINVAL;
+    }
+    if (precision == MG_PREC_MIXED && !c->mixed) {
+        set_err(c, "FP32 kernels need a context set up with MG_PREC_MIXED");
+        return MG_EINVAL;
+    }
+    return MG_OK;
+}
+
+template <typename S, typename D>
+int convert(mg_ctx* c, const S* x, long n, D* y)
+{
+    k_convert<S, D><<<grid_for(n), kBlock, 0, c->stream>>>(x, n, y);
+    CHECK_LAUNCH(c);
+    return MG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+int mg_plan_levels(const int dims[3], int coarse_max)
+{
+    if (!dims) return 0;
+    return plan(dims[0], dims[1], dims[2], coarse_max, nullptr);
+}
+
+int mg_setup(mg_ctx** out, const double* beta_x, const double* beta_y, const double* beta_z, const int dims[3],
+             double h, int bc, const mg_opts* opts, void* hip_stream)
+{
+    if (!out) return MG_EINVAL;
+    *out = nullptr;
+    const double t0 = now_ms();
+    mg_ctx* c = new (std::nothrow) mg_ctx();
+    if (!c) return MG_ENOMEM;
+    c->err[0] = 0;
+    c->opts = opts ? *opts : mg_opts{2, 2, 100, 4, MG_PREC_FP64, 0};
+    const mg_opts& o = c->opts;
+    g_setup_err[0] = 0;
+    auto fail = [&](int status) {
+        std::snprintf(g_setup_err, sizeof(g_setup_err), "%s", c->err);
+        free_ctx(c);
+        return status;
+    };
+    if (!beta_x || !beta_y || !beta_z || !dims) {
+        set_err(c, "NULL argument");
+        return fail(MG_EINVAL);
+    }
+    if (bc != MG_BC_NEUMANN) {
+        set_err(c, "only MG_BC_NEUMANN is supported");
+        return fail(MG_EINVAL);
+    }
+    if (!(h > 0.0) || !std::isfinite(h)) {
+        set_err(c, "h must be finite and > 0");
+        return fail(MG_EINVAL);
+    }
+    if (o.pre < 0 || o.pre > 8 || o.post < 0 || o.post > 8 || o.pre + o.post == 0 || o.max_cycles < 1 ||
+        o.max_cycles >= MG_HIST_MAX || o.coarse_max < 1 || o.coarse_max > 4 ||
+        (o.precision != MG_PREC_FP64 && o.precision != MG_PREC_MIXED) ||
+        (o.flags & ~(MG_FLAG_ZERO_GUESS | MG_FLAG_TIMING))) {
+        set_err(c, "invalid options");
+        return fail(MG_EINVAL);
+    }
+    Dims ds[MG_MAX_LEVELS];
+    const int nlev = plan(dims[0], dims[1], dims[2], o.coarse_max, ds);
+    if (nlev == 0) {
+        set_err(c, "dims %d x %d x %d cannot be coarsened to <= %d per dimension by halving", dims[0], dims[1],
+                dims[2], o.coarse_max);
+        return fail(MG_EINVAL);
+    }
+    c->nlev = nlev;
+    c->mixed = o.precision == MG_PREC_MIXED;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    double hl = h;
+    for (int l = 0; l < nlev; ++l) {
+        c->lev[l].d = ds[l];
+        c->lev[l].n = (long)ds[l].nx * ds[l].ny * ds[l].nz;
+        c->lev[l].h = hl;
+        hl *= 2.0;
+    }
+    if (c->lev[nlev - 1].n > kMaxCoarseCells) {
+        set_err(c, "coarsest grid has more than %d cells", kMaxCoarseCells);
+        return fail(MG_EINVAL);
+    }
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        set_err(c, "no HIP device");
+        return fail(MG_EHIP);
+    }
+    Arena sizing{nullptr, 0, 0};
+    carve(c, sizing);
+    c->arena_bytes = sizing.off;
+    if (hipMalloc(&c->arena, c->arena_bytes) != hipSuccess) {
+        set_err(c, "hipMalloc of %zu bytes failed", c->arena_bytes);
+        (void)hipGetLastError();
+        return fail(MG_ENOMEM);
+    }
+    Arena a{static_cast<char*>(c->arena), 0, c->arena_bytes};
+    carve(c, a);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->host_scal), sizeof(double) * 16, hipHostMallocDefault) !=
+        hipSuccess) {
+        set_err(c, "pinned host allocation failed");
+        return fail(MG_ENOMEM);
+    }
+    if (o.flags & MG_FLAG_TIMING) {
+        c->ev = new (std::nothrow) hipEvent_t[2 * kTimingPairs]();
+        if (!c->ev) return fail(MG_ENOMEM);
+        for (int t = 0; t < 2 * kTimingPairs; ++t)
+            if (hipEventCreate(&c->ev[t]) != hipSuccess) {
+                set_err(c, "hipEventCreate failed");
+                return fail(MG_EHIP);
+            }
+    }
+    const int st = setup_impl(c, beta_x, beta_y, beta_z);
+    if (st != MG_OK) return fail(st);
+    c->valid = true;
+    c->setup_ms = now_ms() - t0;
+    *out = c;
+    return MG_OK;
+}
+
+int mg_update(mg_ctx* c, const double* beta_x, const double* beta_y, const double* beta_z)
+{
+    TRY(check_ctx(c));
+    if (!beta_x || !beta_y || !beta_z) {
+        set_err(c, "NULL argument");
+        return MG_EINVAL;
+    }
+    const double t0 = now_ms();
+    c->valid = false;
+    TRY(setup_impl(c, beta_x, beta_y, beta_z));
+    c->valid = true;
+    c->setup_ms = now_ms() - t0;
+    return MG_OK;
+}
+
+int mg_solve(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st)
+{
+    TRY(check_ctx(c));
+    return solve_impl(c, rhs, p, tol, st);
+}
+
+int mg_solve_adjoint(mg_ctx* c, const double* g, double* lambda, double tol, mg_stats* st)
+{
+    TRY(check_ctx(c));
+    return solve_impl(c, g, lambda, tol, st);
+}
+
+int mg_face_grad(mg_ctx* c, const double* lambda, const double* p, double* g_x, double* g_y, double* g_z)
+{
+    TRY(check_ctx(c));
+    if (!lambda || !p || !g_x || !g_y || !g_z) {
+        set_err(c, "NULL argument");
+        return MG_EINVAL;
+    }
+    Level& F = c->lev[0];
+    const long total = (long)F.d.nz * F.d.ny * (F.d.nx + 1) + (long)F.d.nz * (F.d.ny + 1) * F.d.nx +
+                       (long)(F.d.nz + 1) * F.d.ny * F.d.nx;
+    k_face_grad<<<grid_for(total), kBlock, 0, c->stream>>>(lambda, p, F.d, 1.0 / (F.h * F.h), g_x, g_y, g_z);
+    CHECK_LAUNCH(c);
+    return MG_OK;
+}
+
+int mg_apply(mg_ctx* c, const double* x, double* y)
+{
+    TRY(check_ctx(c));
+    if (!x || !y || x == y) {
+        set_err(c, "x and y must be distinct non-NULL device pointers");
+        return MG_EINVAL;
+    }
+    Level& F = c->lev[0];
+    k_apply<<<grid_for(F.n), kBlock, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, F.d, 1.0 / (F.h * F.h), x, y);
+    CHECK_LAUNCH(c);
+    return MG_OK;
+}
+
+void mg_destroy(mg_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    free_ctx(c);
+}
+
+const char* mg_last_error(const mg_ctx* c)
+{
+    if (!c) return g_setup_err;
+    return c->err;
+}
+
+int mg_faces_from_vof(const double* f_drop, const double* f_film, const int dims[3], double rho_drop,
+                      double rho_film, double rho_gas, double* beta_x, double* beta_y, double* beta_z,
+                      void* hip_stream)
+{
+    if (!f_drop || !f_film || !dims || !beta_x || !beta_y || !beta_z) return MG_EINVAL;
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return MG_EINVAL;
+    if (!(rho_drop > 0) || !(rho_film > 0) || !(rho_gas > 0)) return MG_EINVAL;
+    const Dims d{dims[0], dims[1], dims[2]};
+    const long total = (long)d.nz * d.ny * (d.nx + 1) + (long)d.nz * (d.ny + 1) * d.nx +
+                       (long)(d.nz + 1) * d.ny * d.nx;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    k_faces_from_vof<<<grid_for(total), kBlock, 0, s>>>(f_drop, f_film, d, rho_drop, rho_film, rho_gas, beta_x,
+                                                        beta_y, beta_z);
+    return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
+}
+
+int mg_divergence(const double* u, const double* v, const double* w, const int dims[3], double h, double dt,
+                  double* b, void* hip_stream)
+{
+    if (!u || !v || !w || !dims || !b) return MG_EINVAL;
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || !(h > 0) || !(dt > 0)) return MG_EINVAL;
+    const Dims d{dims[0], dims[1], dims[2]};
+    const long n = (long)d.nx * d.ny * d.nz;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    k_divergence<<<grid_for(n), kBlock, 0, s>>>(u, v, w, d, h, dt, b);
+    return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
+}
+
+int mg_level_info(const mg_ctx* cc, int level, int dims[3], double* h)
+{
+    mg_ctx* c = as_ctx(cc);
+    if (!c) return MG_EINVAL;
+    if (level < 0 || level >= c->nlev) return MG_EINVAL;
+    if (dims) {
+        dims[0] = c->lev[level].d.nx;
+        dims[1] = c->lev[level].d.ny;
+        dims[2] = c->lev[level].d.nz;
+    }
+    if (h) *h = c->lev[level].h;
+    return MG_OK;
+}
+
+int mg_level_faces(mg_ctx* c, int level, double* beta_x, double* beta_y, double* beta_z)
+{
+    TRY(check_ctx(c));
+    TRY(level_ok(c, level, MG_PREC_FP64));
+    if (!beta_x || !beta_y || !beta_z) return MG_EINVAL;
+    Level& L = c->lev[level];
+    const long total = (long)L.d.nz * L.d.ny * (L.d.nx + 1) + (long)L.d.nz * (L.d.ny + 1) * L.d.nx +
+                       (long)(L.d.nz + 1) * L.d.ny * L.d.nx;
+    k_export_faces<double><<<grid_for(total), kBlock, 0, c->stream>>>(L.f64.bx, L.f64.by, L.f64.bz, L.d, beta_x,
+                                                                      beta_y, beta_z);
+    CHECK_LAUNCH(c);
+    return MG_OK;
+}
+
+int mg_smooth(mg_ctx* c, int level, int precision, const double* b, double* p, int nsweeps, int order)
+{
+    TRY(check_ctx(c));
+    TRY(level_ok(c, level, precision));
+    if (!b || !p || nsweeps < 0 || (order != 0 && order != 1)) {
+        set_err(c, "invalid smoothing arguments");
+        return MG_EINVAL;
+    }
+    Level& L = c->lev[level];
+    if (precision == MG_PREC_FP64) {
+        double* x = level == 0 ? c->work : L.f64.x;
+        double* t = level == 0 ? c->ptmp : L.f64.t;
+        HIP_TRY(c, hipMemcpyAsync(x, p, sizeof(double) * L.n, hipMemcpyDeviceToDevice, c->stream));
+        for (int s = 0; s < nsweeps; ++s) {
+            TRY(sweep<double>(c, level, b, x, t, order, false));
+            std::swap(x, t);
+        }
+        HIP_TRY(c, hipMemcpyAsync(p, x, sizeof(double) * L.n, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        float* x = L.f32.x;
+        float* t = L.f32.t;
+        float* bb = L.f32.b;
+        TRY(convert<double, float>(c, b, L.n, bb));
+        TRY(convert<double, float>(c, p, L.n, x));
+        for (int s = 0; s < nsweeps; ++s) {
+            TRY(sweep<float>(c, level, bb, x, t, order, false));
+            std::swap(x, t);
+        }
+        TRY(convert<float, double>(c, x, L.n, p));
+    }
+    return MG_OK;
+}
+
+int mg_residual_restrict(mg_ctx* c, int level, int precision, const double* b, const double* p,
+                         double* b_coarse)
+{
+    TRY(check_ctx(c));
+    TRY(level_ok(c, level, precision));
+    if (level >= c->nlev - 1) {
+        set_err(c, "level %d has no coarser level", level);
+        return MG_EINVAL;
+    }
+    if (!b || !p || !b_coarse) return MG_EINVAL;
+    Level& L = c->lev[level];
+    Level& C = c->lev[level + 1];
+    if (precision == MG_PREC_FP64) {
+        TRY(residual_restrict<double>(c, level, b, p, b_coarse));
+    } else {
+        TRY(convert<double, float>(c, b, L.n, L.f32.b));
+        TRY(convert<double, float>(c, p, L.n, L.f32.x));
+        TRY(residual_restrict<float>(c, level, L.f32.b, L.f32.x, C.f32.b));
+        TRY(convert<float, double>(c, C.f32.b, C.n, b_coarse));
+    }
+    return MG_OK;
+}
+
+int mg_prolong_correct(mg_ctx* c, int level, int precision, const double* e_coarse, double* p)
+{
+    TRY(check_ctx(c));
+    TRY(level_ok(c, level, precision));
+    if (level >= c->nlev - 1) {
+        set_err(c, "level %d has no coarser level", level);
+        return MG_EINVAL;
+    }
+    if (!e_coarse || !p) return MG_EINVAL;
+    Level& L = c->lev[level];
+    Level& C = c->lev[level + 1];
+    if (precision == MG_PREC_FP64) {
+        TRY(prolong_correct<double>(c, level, e_coarse, p));
+    } else {
+        TRY(convert<double, float>(c, e_coarse, C.n, C.f32.x));
+        TRY(convert<double, float>(c, p, L.n, L.f32.x));
+        TRY(prolong_correct<float>(c, level, C.f32.x, L.f32.x));
+        TRY(convert<float, double>(c, L.f32.x, L.n, p));
+    }
+    return MG_OK;
+}
+
+int mg_coarse_solve(mg_ctx* c, const double* r, double* e)
+{
+    TRY(check_ctx(c));
+    if (!r || !e) return MG_EINVAL;
+    return coarse_apply<double>(c, r, e);
+}
+
+int mg_residual_norm2(mg_ctx* c, const double* b, const double* p, double* norm2)
+{
+    TRY(check_ctx(c));
+    if (!b || !p || !norm2) return MG_EINVAL;
+    TRY(residual_norm_launch(c, b, p, nullptr, 6));
+    HIP_TRY(c, hipMemcpyAsync(c->host_scal + 6, c->scal + 6, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    harvest(c);
+    *norm2 = c->host_scal[6];
+    return MG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,601 @@
+// Device kernels of the multigrid pressure-Poisson solver (gfx950).
+//
+// Internal layout of a level with nx*ny*nz cells (x fastest):
+//   cell arrays          T[n]
+//   face coefficients    three T[n] arrays holding, per cell, the coefficient
+//                        of its LOW face in x, y and z.  The low face of a cell
+//                        on the low wall is stored as 0; the high face of a
+//                        cell is the low face of the next cell, or a wall.
+// Every stencil kernel therefore reads one coefficient per face and never
+// needs the (nx+1)-padded public layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mgp {
+
+constexpr int kBlock = 256;          // threads per block of the generic kernels
+constexpr int kReduceBlocks = 1024;  // fixed partial count -> deterministic reductions
+
+struct Dims {
+    int nx, ny, nz;
+};
+
+// ---------------------------------------------------------------------------
+// reductions: fixed-shape block partials, then one block sums them in order
+// ---------------------------------------------------------------------------
+
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over the block; the result is valid in thread 0.  blockDim.x == kBlock.
+__device__ inline double block_sum(double v)
+{
+    __shared__ double ws[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) ws[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < kBlock / 64; ++w) s += ws[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+// out[slot] = sum of partials[0..count)
+__global__ void k_reduce_final(const double* __restrict__ partials, int count, double* __restrict__ out,
+                               int slot)
+{
+    double v = 0.0;
+    for (int t = threadIdx.x; t < count; t += kBlock) v += partials[t];
+    v = block_sum(v);
+    if (threadIdx.x == 0) out[slot] = v;
+}
+
+template <typename T>
+__global__ void k_sum(const T* __restrict__ x, long n, double* __restrict__ partials)
+{
+    double v = 0.0;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock)
+        v += (double)x[c];
+    v = block_sum(v);
+    if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+// y = x - scal[slot] * scale, partial sums of y^2
+__global__ void k_sub_scalar_norm(const double* __restrict__ x, long n, const double* __restrict__ scal,
+                                  int slot, double scale, double* __restrict__ y,
+                                  double* __restrict__ partials)
+{
+    const double mu = scal[slot] * scale;
+    double v = 0.0;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
+        double t = x[c] - mu;
+        y[c] = t;
+        v += t * t;
+    }
+    v = block_sum(v);
+    if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+// x -= scal[slot] * scale
+__global__ void k_sub_scalar(double* __restrict__ x, long n, const double* __restrict__ scal, int slot,
+                             double scale)
+{
+    const double mu = scal[slot] * scale;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock)
+        x[c] -= mu;
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, long n, T v)
+{
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) x[c] = v;
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S* __restrict__ x, long n, D* __restrict__ y)
+{
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock)
+        y[c] = (D)x[c];
+}
+
+// ---------------------------------------------------------------------------
+// face coefficients: import, validation, coarsening
+// ---------------------------------------------------------------------------
+
+__device__ inline void cell_of(long c, const Dims d, int& i, int& j, int& k)
+{
+    const unsigned cc = (unsigned)c;
+    const unsigned row = cc / (unsigned)d.nx;
+    i = (int)(cc - row * (unsigned)d.nx);
+    k = (int)(row / (unsigned)d.ny);
+    j = (int)(row - (unsigned)k * (unsigned)d.ny);
+}
+
+__device__ inline bool bad_coeff(double v)
+{
+    return !(v > 0.0) || !(v < INFINITY);  // NaN, <= 0 or +Inf
+}
+
+// public face layouts -> internal low-face arrays; partial count of invalid interior entries
+__global__ void k_import_faces(const double* __restrict__ pbx, const double* __restrict__ pby,
+                               const double* __restrict__ pbz, Dims d, double* __restrict__ bx,
+                               double* __restrict__ by, double* __restrict__ bz,
+                               double* __restrict__ partials)
+{
+    const long n = (long)d.nx * d.ny * d.nz;
+    double bad = 0.0;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
+        int i, j, k;
+        cell_of(c, d, i, j, k);
+        const long fx = ((long)k * d.ny + j) * (d.nx + 1) + i;
+        const long fy = ((long)k * (d.ny + 1) + j) * d.nx + i;
+        const long fz = c;  // z-face layout [nz+1][ny][nx]: low face of cell c has index c
+        double vx = 0.0, vy = 0.0, vz = 0.0;
+        if (i > 0) { vx = pbx[fx]; bad += bad_coeff(vx) ? 1.0 : 0.0; }
+        if (j > 0) { vy = pby[fy]; bad += bad_coeff(vy) ? 1.0 : 0.0; }
+        if (k > 0) { vz = pbz[fz]; bad += bad_coeff(vz) ? 1.0 : 0.0; }
+        bx[c] = vx;
+        by[c] = vy;
+        bz[c] = vz;
+    }
+    bad = block_sum(bad);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bad;
+}
+
+// internal low-face arrays of a level -> public face layouts (walls written as 0)
+template <typename T>
+__global__ void k_export_faces(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
+                               Dims d, double* __restrict__ pbx, double* __restrict__ pby,
+                               double* __restrict__ pbz)
+{
+    const long nfx = (long)d.nz * d.ny * (d.nx + 1);
+    const long nfy = (long)d.nz * (d.ny + 1) * d.nx;
+    const long nfz = (long)(d.nz + 1) * d.ny * d.nx;
+    const long total = nfx + nfy + nfz;
+    for (long f = (long)blockIdx.x * kBlock + threadIdx.x; f < total; f += (long)gridDim.x * kBlock) {
+        if (f < nfx) {
+            const int i = (int)(f % (d.nx + 1));
+            const long row = f / (d.nx + 1);
+            pbx[f] = (i == 0 || i == d.nx) ? 0.0 : (double)bx[row * d.nx + i];
+        } else if (f < nfx + nfy) {
+            const long g = f - nfx;
+            const int i = (int)(g % d.nx);
+            const long r = g / d.nx;
+            const int j = (int)(r % (d.ny + 1));
+            const int k = (int)(r / (d.ny + 1));
+            pby[g] = (j == 0 || j == d.ny) ? 0.0 : (double)by[((long)k * d.ny + j) * d.nx + i];
+        } else {
+            const long g = f - nfx - nfy;
+            const int k = (int)(g / ((long)d.ny * d.nx));
+            pbz[g] = (k == 0 || k == d.nz) ? 0.0 : (double)bz[g];
+        }
+    }
+}
+
+// coarse low face = mean of the 4 fine low faces that tile it (wall faces stay 0)
+__global__ void k_coarsen_faces(const double* __restrict__ fbx, const double* __restrict__ fby,
+                                const double* __restrict__ fbz, Dims f, Dims c, double* __restrict__ cbx,
+                                double* __restrict__ cby, double* __restrict__ cbz)
+{
+    const long n = (long)c.nx * c.ny * c.nz;
+    const long fs = (long)f.nx * f.ny;
+    for (long C = (long)blockIdx.x * kBlock + threadIdx.x; C < n; C += (long)gridDim.x * kBlock) {
+        int I, J, K;
+        cell_of(C, c, I, J, K);
+        const long f0 = (long)(2 * K) * fs + (long)(2 * J) * f.nx + 2 * I;  // fine cell (2I, 2J, 2K)
+        double vx = 0.0, vy = 0.0, vz = 0.0;
+        if (I > 0) vx = (fbx[f0] + fbx[f0 + f.nx] + fbx[f0 + fs] + fbx[f0 + fs + f.nx]) / 4.0;
+        if (J > 0) vy = (fby[f0] + fby[f0 + 1] + fby[f0 + fs] + fby[f0 + fs + 1]) / 4.0;
+        if (K > 0) vz = (fbz[f0] + fbz[f0 + 1] + fbz[f0 + f.nx] + fbz[f0 + f.nx + 1]) / 4.0;
+        cbx[C] = vx;
+        cby[C] = vy;
+        cbz[C] = vz;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// exact coarsest-grid inverse (setup, one block)
+// ---------------------------------------------------------------------------
+
+// Builds the bordered matrix M = [[L, 1], [1^T, 0]] (m = n+1) of the coarsest
+// level next to an identity, reduces it by Gauss-Jordan elimination with
+// partial pivoting, and stores G = top-left n x n block of M^-1: for any r,
+// G r is the zero-mean solution of L e = r - mean(r).
+// work: m * 2m doubles; status[0] = 0 on success, 1 if singular.
+__global__ void k_coarse_inverse(const double* __restrict__ bx, const double* __restrict__ by,
+                                 const double* __restrict__ bz, Dims d, double h, double* __restrict__ work,
+                                 double* __restrict__ G, double* __restrict__ status)
+{
+    const int n = d.nx * d.ny * d.nz, m = n + 1, w = 2 * m;
+    const double h2 = h * h;
+    __shared__ int piv_row;
+    __shared__ int singular;
+    for (int t = threadIdx.x; t < m * w; t += blockDim.x) work[t] = 0.0;
+    if (threadIdx.x == 0) singular = 0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < m; c += blockDim.x) {
+        double* row = work + (long)c * w;
+        row[m + c] = 1.0;
+        if (c == n) {
+            for (int t = 0; t < n; ++t) row[t] = 1.0;
+            continue;
+        }
+        const int i = c % d.nx, j = (c / d.nx) % d.ny, k = c / (d.nx * d.ny);
+        const int sy = d.nx, sz = d.nx * d.ny;
+        double diag = 0.0, bf;
+        if (i > 0)        { bf = bx[c];      row[c - 1] += bf / h2;  diag -= bf / h2; }
+        if (i < d.nx - 1) { bf = bx[c + 1];  row[c + 1] += bf / h2;  diag -= bf / h2; }
+        if (j > 0)        { bf = by[c];      row[c - sy] += bf / h2; diag -= bf / h2; }
+        if (j < d.ny - 1) { bf = by[c + sy]; row[c + sy] += bf / h2; diag -= bf / h2; }
+        if (k > 0)        { bf = bz[c];      row[c - sz] += bf / h2; diag -= bf / h2; }
+        if (k < d.nz - 1) { bf = bz[c + sz]; row[c + sz] += bf / h2; diag -= bf / h2; }
+        row[c] += diag;
+        row[n] = 1.0;
+    }
+    __syncthreads();
+    for (int col = 0; col < m; ++col) {
+        if (threadIdx.x == 0) {
+            int p = col;
+            double best = fabs(work[(long)col * w + col]);
+            for (int r = col + 1; r < m; ++r) {
+                const double a = fabs(work[(long)r * w + col]);
+                if (a > best) { best = a; p = r; }
+            }
+            piv_row = p;
+            if (best == 0.0) singular = 1;
+        }
+        __syncthreads();
+        if (singular) break;
+        const int p = piv_row;
+        if (p != col) {
+            for (int t = threadIdx.x; t < w; t += blockDim.x) {
+                const double a = work[(long)col * w + t];
+                work[(long)col * w + t] = work[(long)p * w + t];
+                work[(long)p * w + t] = a;
+            }
+        }
+        __syncthreads();
+        const double inv = 1.0 / work[(long)col * w + col];
+        __syncthreads();
+        for (int t = threadIdx.x; t < w; t += blockDim.x) work[(long)col * w + t] *= inv;
+        __syncthreads();
+        // eliminate column `col` from every other row; the pivot row is read-only here
+        for (int e = threadIdx.x; e < m * w; e += blockDim.x) {
+            const int r = e / w, t = e % w;
+            if (r == col) continue;
+            const double f = work[(long)r * w + col];
+            if (t != col) work[(long)r * w + t] -= f * work[(long)col * w + t];
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < m; r += blockDim.x)
+            if (r != col) work[(long)r * w + col] = 0.0;
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int r = e / n, t = e % n;
+        G[e] = work[(long)r * w + m + t];
+    }
+    if (threadIdx.x == 0) status[0] = singular ? 1.0 : 0.0;
+}
+
+// e = G r on the coarsest level (n <= 64 cells), accumulated in FP64
+template <typename T>
+__global__ void k_coarse_apply(const double* __restrict__ G, int n, const T* __restrict__ r, T* __restrict__ e)
+{
+    __shared__ double rs[64];
+    const int t = threadIdx.x;
+    if (t < n) rs[t] = (double)r[t];
+    __syncthreads();
+    if (t < n) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += G[(long)t * n + j] * rs[j];
+        e[t] = (T)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stencil helpers
+// ---------------------------------------------------------------------------
+
+// diag = sum of coupled face coefficients, off = sum beta_f * x_neighbour
+template <typename T, typename X>
+__device__ inline void stencil(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
+                               const X* x, const Dims d, int i, int j, int k, long c, T& diag, T& off)
+{
+    const long sy = d.nx, sz = (long)d.nx * d.ny;
+    T dg = 0, of = 0, f;
+    if (i > 0)        { f = bx[c];      dg += f; of += f * (T)x[c - 1]; }
+    if (i < d.nx - 1) { f = bx[c + 1];  dg += f; of += f * (T)x[c + 1]; }
+    if (j > 0)        { f = by[c];      dg += f; of += f * (T)x[c - sy]; }
+    if (j < d.ny - 1) { f = by[c + sy]; dg += f; of += f * (T)x[c + sy]; }
+    if (k > 0)        { f = bz[c];      dg += f; of += f * (T)x[c - sz]; }
+    if (k < d.nz - 1) { f = bz[c + sz]; dg += f; of += f * (T)x[c + sz]; }
+    diag = dg;
+    off = of;
+}
+
+// ---------------------------------------------------------------------------
+// reference-shaped kernels: apply, residual norm, half-sweeps, transfers
+// ---------------------------------------------------------------------------
+
+// y = L x
+__global__ void k_apply(const double* __restrict__ bx, const double* __restrict__ by,
+                        const double* __restrict__ bz, Dims d, double inv_h2, const double* __restrict__ x,
+                        double* __restrict__ y)
+{
+    const long n = (long)d.nx * d.ny * d.nz;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
+        int i, j, k;
+        cell_of(c, d, i, j, k);
+        double dg, of;
+        stencil(bx, by, bz, x, d, i, j, k, c, dg, of);
+        y[c] = (of - dg * x[c]) * inv_h2;
+    }
+}
+
+// partials of ||b - L p||^2 (optionally storing r)
+__global__ void k_residual_norm(const double* __restrict__ bx, const double* __restrict__ by,
+                                const double* __restrict__ bz, Dims d, double inv_h2,
+                                const double* __restrict__ b, const double* __restrict__ p,
+                                double* __restrict__ r_out, double* __restrict__ partials)
+{
+    const long n = (long)d.nx * d.ny * d.nz;
+    double acc = 0.0;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
+        int i, j, k;
+        cell_of(c, d, i, j, k);
+        double dg, of;
+        stencil(bx, by, bz, p, d, i, j, k, c, dg, of);
+        const double r = b[c] - (of - dg * p[c]) * inv_h2;
+        if (r_out) r_out[c] = r;
+        acc += r * r;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// One Gauss-Seidel half-sweep over colour `colour` ((i+j+k)&1 == colour):
+//   dst_c = (sum beta_f src_nb - h^2 b_c) / sum beta_f
+// src holds the other colour (it may alias dst).  With zero_src the other
+// colour is taken as 0.  A cell with no coupled face copies its old value.
+// Launch: grid (ceil(ceil(nx/2)/64), ceil(ny/4), nz), block (64, 4).
+template <typename T>
+__global__ void k_half_sweep(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
+                             Dims d, T h2, const T* __restrict__ b, const T* src, T* dst, int colour,
+                             int zero_src)
+{
+    const int m = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.y * 4 + threadIdx.y;
+    const int k = blockIdx.z;
+    if (j >= d.ny) return;
+    const int i = 2 * m + ((j + k + colour) & 1);
+    if (i >= d.nx) return;
+    const long c = ((long)k * d.ny + j) * d.nx + i;
+    T dg, of;
+    if (zero_src) {
+        const long sy = d.nx, sz = (long)d.nx * d.ny;
+        dg = 0;
+        if (i > 0) dg += bx[c];
+        if (i < d.nx - 1) dg += bx[c + 1];
+        if (j > 0) dg += by[c];
+        if (j < d.ny - 1) dg += by[c + sy];
+        if (k > 0) dg += bz[c];
+        if (k < d.nz - 1) dg += bz[c + sz];
+        of = 0;
+    } else {
+        stencil(bx, by, bz, src, d, i, j, k, c, dg, of);
+    }
+    T v;
+    if (dg > (T)0) v = (of - h2 * b[c]) / dg;
+    else v = zero_src ? (T)0 : src[c];
+    dst[c] = v;
+}
+
+// b_coarse = mean over the 8 children of (b - L x) (fine dims f, coarse dims c)
+template <typename T>
+__global__ void k_residual_restrict(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
+                                    Dims f, Dims cd, T inv_h2, const T* __restrict__ b, const T* __restrict__ x,
+                                    T* __restrict__ bc)
+{
+    const long n = (long)cd.nx * cd.ny * cd.nz;
+    for (long C = (long)blockIdx.x * kBlock + threadIdx.x; C < n; C += (long)gridDim.x * kBlock) {
+        int I, J, K;
+        cell_of(C, cd, I, J, K);
+        T s = 0;
+        for (int cz = 0; cz < 2; ++cz)
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx) {
+                    const int i = 2 * I + cx, j = 2 * J + cy, k = 2 * K + cz;
+                    const long c = ((long)k * f.ny + j) * f.nx + i;
+                    T dg, of;
+                    stencil(bx, by, bz, x, f, i, j, k, c, dg, of);
+                    s += b[c] - (of - dg * x[c]) * inv_h2;
+                }
+        bc[C] = s * (T)0.125;
+    }
+}
+
+// x_fine += trilinear prolongation of the coarse correction e
+template <typename T>
+__global__ void k_prolong_correct(Dims f, Dims cd, const T* __restrict__ e, T* __restrict__ x)
+{
+    const long n = (long)f.nx * f.ny * f.nz;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
+        int i, j, k;
+        cell_of(c, f, i, j, k);
+        const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+        int I1 = (i & 1) ? I0 + 1 : I0 - 1;
+        int J1 = (j & 1) ? J0 + 1 : J0 - 1;
+        int K1 = (k & 1) ? K0 + 1 : K0 - 1;
+        I1 = I1 < 0 ? 0 : (I1 > cd.nx - 1 ? cd.nx - 1 : I1);
+        J1 = J1 < 0 ? 0 : (J1 > cd.ny - 1 ? cd.ny - 1 : J1);
+        K1 = K1 < 0 ? 0 : (K1 > cd.nz - 1 ? cd.nz - 1 : K1);
+        const long sy = cd.nx, sz = (long)cd.nx * cd.ny;
+        auto E = [&](int a, int bb, int cc) { return e[(long)cc * sz + (long)bb * sy + a]; };
+        // x-direction first, then y, then z: weights 3/4 (parent) and 1/4 (side)
+        const T q = (T)0.75, o = (T)0.25;
+        const T e00 = q * E(I0, J0, K0) + o * E(I1, J0, K0);
+        const T e10 = q * E(I0, J1, K0) + o * E(I1, J1, K0);
+        const T e01 = q * E(I0, J0, K1) + o * E(I1, J0, K1);
+        const T e11 = q * E(I0, J1, K1) + o * E(I1, J1, K1);
+        const T f0 = q * e00 + o * e10;
+        const T f1 = q * e01 + o * e11;
+        x[c] += q * f0 + o * f1;
+    }
+}
+
+// Mixed-precision outer step (FP64):
+//   q = p + e (e FP32), r = b - L q, r32 = (float) r, partials of ||r||^2.
+// q is written to p_out (must not alias p_in).
+__global__ void k_outer_update(const double* __restrict__ bx, const double* __restrict__ by,
+                               const double* __restrict__ bz, Dims d, double inv_h2,
+                               const double* __restrict__ b, const double* __restrict__ p_in,
+                               const float* __restrict__ e, int zero_e, double* __restrict__ p_out,
+                               float* __restrict__ r32, double* __restrict__ partials)
+{
+    const long n = (long)d.nx * d.ny * d.nz;
+    const long sy = d.nx, sz = (long)d.nx * d.ny;
+    double acc = 0.0;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
+        int i, j, k;
+        cell_of(c, d, i, j, k);
+        auto Q = [&](long t) { return zero_e ? p_in[t] : p_in[t] + (double)e[t]; };
+        double dg = 0.0, of = 0.0, f;
+        if (i > 0)        { f = bx[c];      dg += f; of += f * Q(c - 1); }
+        if (i < d.nx - 1) { f = bx[c + 1];  dg += f; of += f * Q(c + 1); }
+        if (j > 0)        { f = by[c];      dg += f; of += f * Q(c - sy); }
+        if (j < d.ny - 1) { f = by[c + sy]; dg += f; of += f * Q(c + sy); }
+        if (k > 0)        { f = bz[c];      dg += f; of += f * Q(c - sz); }
+        if (k < d.nz - 1) { f = bz[c + sz]; dg += f; of += f * Q(c + sz); }
+        const double qc = Q(c);
+        const double r = b[c] - (of - dg * qc) * inv_h2;
+        p_out[c] = qc;
+        r32[c] = (float)r;
+        acc += r * r;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// g_f = (lambda_R - lambda_L)(p_R - p_L)/h^2 on interior faces, 0 on walls (public face layouts)
+__global__ void k_face_grad(const double* __restrict__ lam, const double* __restrict__ p, Dims d, double inv_h2,
+                            double* __restrict__ gx, double* __restrict__ gy, double* __restrict__ gz)
+{
+    const long nfx = (long)d.nz * d.ny * (d.nx + 1);
+    const long nfy = (long)d.nz * (d.ny + 1) * d.nx;
+    const long nfz = (long)(d.nz + 1) * d.ny * d.nx;
+    const long total = nfx + nfy + nfz;
+    const long sz = (long)d.nx * d.ny;
+    for (long f = (long)blockIdx.x * kBlock + threadIdx.x; f < total; f += (long)gridDim.x * kBlock) {
+        if (f < nfx) {
+            const int i = (int)(f % (d.nx + 1));
+            const long row = f / (d.nx + 1);
+            double g = 0.0;
+            if (i > 0 && i < d.nx) {
+                const long c = row * d.nx + i;
+                g = (lam[c] - lam[c - 1]) * (p[c] - p[c - 1]) * inv_h2;
+            }
+            gx[f] = g;
+        } else if (f < nfx + nfy) {
+            const long t = f - nfx;
+            const int i = (int)(t % d.nx);
+            const long r = t / d.nx;
+            const int j = (int)(r % (d.ny + 1));
+            const int k = (int)(r / (d.ny + 1));
+            double g = 0.0;
+            if (j > 0 && j < d.ny) {
+                const long c = ((long)k * d.ny + j) * d.nx + i;
+                g = (lam[c] - lam[c - d.nx]) * (p[c] - p[c - d.nx]) * inv_h2;
+            }
+            gy[t] = g;
+        } else {
+            const long t = f - nfx - nfy;
+            const int k = (int)(t / sz);
+            double g = 0.0;
+            if (k > 0 && k < d.nz) g = (lam[t] - lam[t - sz]) * (p[t] - p[t - sz]) * inv_h2;
+            gz[t] = g;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// inputs of the solve (contraction off: each product rounds, as written)
+// ---------------------------------------------------------------------------
+
+__device__ inline double cell_density(double fd, double ff, double rd, double rf, double rg)
+{
+#pragma clang fp contract(off)
+    double fg = 1.0 - fd - ff;
+    fg = fg < 0.0 ? 0.0 : fg;
+    return rd * fd + rf * ff + rg * fg;
+}
+
+__global__ void k_faces_from_vof(const double* __restrict__ fd, const double* __restrict__ ff, Dims d,
+                                 double rd, double rf, double rg, double* __restrict__ gx,
+                                 double* __restrict__ gy, double* __restrict__ gz)
+{
+#pragma clang fp contract(off)
+    const long nfx = (long)d.nz * d.ny * (d.nx + 1);
+    const long nfy = (long)d.nz * (d.ny + 1) * d.nx;
+    const long nfz = (long)(d.nz + 1) * d.ny * d.nx;
+    const long total = nfx + nfy + nfz;
+    const long sz = (long)d.nx * d.ny;
+    for (long f = (long)blockIdx.x * kBlock + threadIdx.x; f < total; f += (long)gridDim.x * kBlock) {
+        long a = -1, bcell = -1;
+        double* out;
+        long o;
+        if (f < nfx) {
+            const int i = (int)(f % (d.nx + 1));
+            const long row = f / (d.nx + 1);
+            if (i > 0 && i < d.nx) { bcell = row * d.nx + i; a = bcell - 1; }
+            out = gx; o = f;
+        } else if (f < nfx + nfy) {
+            const long t = f - nfx;
+            const int i = (int)(t % d.nx);
+            const long r = t / d.nx;
+            const int j = (int)(r % (d.ny + 1));
+            const int k = (int)(r / (d.ny + 1));
+            if (j > 0 && j < d.ny) { bcell = ((long)k * d.ny + j) * d.nx + i; a = bcell - d.nx; }
+            out = gy; o = t;
+        } else {
+            const long t = f - nfx - nfy;
+            const int k = (int)(t / sz);
+            if (k > 0 && k < d.nz) { bcell = t; a = t - sz; }
+            out = gz; o = t;
+        }
+        double v = 0.0;
+        if (a >= 0) {
+            const double ra = cell_density(fd[a], ff[a], rd, rf, rg);
+            const double rb = cell_density(fd[bcell], ff[bcell], rd, rf, rg);
+            v = 2.0 / (ra + rb);
+        }
+        out[o] = v;
+    }
+}
+
+__global__ void k_divergence(const double* __restrict__ u, const double* __restrict__ v,
+                             const double* __restrict__ w, Dims d, double h, double dt, double* __restrict__ b)
+{
+#pragma clang fp contract(off)
+    const long n = (long)d.nx * d.ny * d.nz;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
+        int i, j, k;
+        cell_of(c, d, i, j, k);
+        const long fx = ((long)k * d.ny + j) * (d.nx + 1) + i;
+        const long fy = ((long)k * (d.ny + 1) + j) * d.nx + i;
+        const long fz = c;
+        const long sz = (long)d.nx * d.ny;
+        const double s = (u[fx + 1] - u[fx]) + (v[fy + d.nx] - v[fy]) + (w[fz + sz] - w[fz]);
+        b[c] = s / h / dt;
+    }
+}
+
+}  // namespace mgp

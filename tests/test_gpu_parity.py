@@ -1,0 +1,299 @@
+"""Parity of the HIP library (through the C ABI) with the CPU oracle.
+
+Each kernel is compared element by element with the oracle's definition on
+seeded inputs at sizes that span several tiles and a ragged tail; whole solves
+are compared cycle by cycle.  Floating-point tolerances:
+  * elementwise inputs (face coefficients, divergence, coarse faces): bit-exact
+    (same operation order, no contraction on either side);
+  * one stencil pass in FP64: 1e-13 relative to the largest magnitude (the GPU
+    contracts products into FMAs, the oracle rounds each product);
+  * FP32 kernels: 2e-6 relative to the largest magnitude;
+  * solves: relative L2 error <= 1e-9 against the oracle's solution converged to
+    1e-13, at a GPU relative residual <= 1e-10 recomputed by the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import refs
+from gpu_util import N, T, gpu_inputs, max_rel, note, oracle_inputs, rel_l2
+from paper_2605_30082_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+S = pytest.importorskip("paper_2605_30082_amd.solver")
+
+DIMS = [(32, 32, 32), (48, 48, 48), (64, 32, 16), (16, 32, 64), (8, 8, 8), (4, 4, 4), (64, 16, 16)]
+
+
+def random_beta(dims, seed=0):
+    nx, ny, nz = dims
+    g = np.random.default_rng(seed)
+    # density-ratio-like spread of coefficients: 1/1000 .. 1/1.2
+    def draw(shape):
+        return 1.0 / g.choice([1000.0, 960.0, 1.2], size=shape) * g.uniform(0.9, 1.1, size=shape)
+    bx = draw((nz, ny, nx + 1))
+    by = draw((nz, ny + 1, nx))
+    bz = draw((nz + 1, ny, nx))
+    return bx, by, bz
+
+
+def random_cells(dims, seed):
+    nx, ny, nz = dims
+    return np.random.default_rng(seed).standard_normal((nz, ny, nx))
+
+
+def make_solver(beta, h, **kw):
+    return S.Solver(T(beta[0]), T(beta[1]), T(beta[2]), h, **kw)
+
+
+# ---------------------------------------------------------------------------
+# inputs of the solve
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("make,n", [(W.sphere_workload, 32), (W.drop_film_workload, 48),
+                                    (W.spheroid_film_workload, 24)])
+def test_faces_and_divergence_bitexact(make, n):
+    note(f"faces/divergence {make.__name__} n={n}")
+    wl = make(n)
+    gb, gd = gpu_inputs(wl)
+    ob, od = oracle_inputs(wl)
+    for a, r in zip(gb, ob):
+        np.testing.assert_array_equal(N(a), r)
+    np.testing.assert_array_equal(N(gd), od)
+
+
+def test_faces_from_vof_with_overfilled_cells():
+    g = np.random.default_rng(5)
+    fd = g.uniform(0, 1, (6, 5, 7))
+    ff = g.uniform(0, 1, (6, 5, 7))   # fd + ff > 1 in many cells: gas clamps at 0
+    gb = S.faces_from_vof(T(fd), T(ff), 1000.0, 930.0, 1.225)
+    ob = oracle.faces_from_vof(fd, ff, 1000.0, 930.0, 1.225)
+    for a, r in zip(gb, ob):
+        np.testing.assert_array_equal(N(a), r)
+
+
+# ---------------------------------------------------------------------------
+# single kernels
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", DIMS)
+def test_apply_and_coarse_faces(dims):
+    note(f"apply/coarse faces dims={dims}")
+    beta = random_beta(dims, 1)
+    h = 1.0 / dims[0]
+    s = make_solver(beta, h)
+    x = random_cells(dims, 2)
+    y = N(s.apply(T(x)))
+    ref = oracle.apply(beta, x, h)
+    assert max_rel(y, ref) < 1e-13
+    # every level's coefficients: bit-exact with the oracle's coarsening
+    ob = beta
+    for lev in range(s.num_levels):
+        (d, hl) = s.level_info(lev)
+        assert hl == h * 2 ** lev
+        gbl = s.level_faces(lev)
+        zb = tuple(a.copy() for a in ob)
+        zb[0][:, :, 0] = zb[0][:, :, -1] = 0
+        zb[1][:, 0, :] = zb[1][:, -1, :] = 0
+        zb[2][0] = zb[2][-1] = 0
+        for a, r in zip(gbl, zb):
+            np.testing.assert_array_equal(N(a), r)
+        if lev + 1 < s.num_levels:
+            ob = oracle.coarsen_faces(ob)
+    s.close()
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_smooth(dims, precision):
+    note(f"smooth dims={dims} {precision}")
+    beta = random_beta(dims, 3)
+    h = 1.0 / dims[0]
+    s = make_solver(beta, h, precision=precision)
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    for lev in range(min(2, s.num_levels)):
+        (d, hl) = s.level_info(lev)
+        lb = [N(a) for a in s.level_faces(lev)]
+        b = random_cells(d, 4 + lev)
+        p = random_cells(d, 6 + lev)
+        for order in (0, 1):
+            for sweeps in (1, 2):
+                got = N(s.smooth(T(b), T(p), level=lev, sweeps=sweeps, order=order, precision=precision))
+                ref = p.copy()
+                colours = (0, 1) if order == 0 else (1, 0)
+                for _ in range(sweeps):
+                    for c in colours:
+                        ref = oracle.rbgs_half(lb, b, ref, hl, c)
+                assert max_rel(got, ref) < tol, (lev, order, sweeps, max_rel(got, ref))
+    s.close()
+
+
+@pytest.mark.parametrize("dims", [d for d in DIMS if d != (4, 4, 4)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_residual_restrict_and_prolong(dims, precision):
+    note(f"restrict/prolong dims={dims} {precision}")
+    beta = random_beta(dims, 7)
+    h = 1.0 / dims[0]
+    s = make_solver(beta, h, precision=precision)
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    for lev in range(s.num_levels - 1):
+        (d, hl) = s.level_info(lev)
+        (dc, _) = s.level_info(lev + 1)
+        lb = [N(a) for a in s.level_faces(lev)]
+        b = random_cells(d, 8)
+        p = random_cells(d, 9)
+        got = N(s.residual_restrict(T(b), T(p), level=lev, precision=precision))
+        ref = oracle.restrict(oracle.residual(lb, b, p, hl))
+        assert max_rel(got, ref) < tol * 10, (lev, max_rel(got, ref))
+        e = random_cells(dc, 10)
+        got = N(s.prolong_correct(T(e), T(p), level=lev, precision=precision))
+        ref = oracle.prolong_add(e, p)
+        assert max_rel(got, ref) < tol, (lev, max_rel(got, ref))
+    s.close()
+
+
+@pytest.mark.parametrize("dims", [(32, 32, 32), (48, 48, 48), (16, 32, 64), (4, 4, 4), (2, 1, 1)])
+def test_coarse_solve(dims):
+    beta = random_beta(dims, 11)
+    h = 1.0 / dims[0]
+    s = make_solver(beta, h)
+    lev = s.num_levels - 1
+    (d, hl) = s.level_info(lev)
+    lb = [N(a) for a in s.level_faces(lev)]
+    r = random_cells(d, 12)
+    got = N(s.coarse_solve(T(r)))
+    ref = oracle.coarse_solve(lb, r, hl)
+    assert max_rel(got, ref) < 1e-11
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# whole solves
+# ---------------------------------------------------------------------------
+
+def test_solve_fp64_lockstep_sphere32():
+    """FP64 GPU solve vs the oracle's identical V-cycle (sphere, 32^3)."""
+    wl = W.sphere_workload(32)
+    gb, gd = gpu_inputs(wl)
+    ob, od = oracle_inputs(wl)
+    s = S.Solver(*gb, wl.h, zero_guess=True)
+    p, st = s.solve(gd, 1e-10)
+    ref = oracle.solve(ob, od, wl.h, tol=1e-10)
+    note(f"gpu cycles {st.cycles} rr {st.rel_res:.3e}; oracle cycles {ref.cycles} rr {ref.rel_res:.3e}")
+    assert st.cycles == ref.cycles
+    np.testing.assert_allclose(st.hist, ref.hist, rtol=1e-8, atol=1e-14)
+    pg = N(p)
+    assert rel_l2(pg, ref.p) < 1e-11
+    exact = oracle.solve(ob, od, wl.h, tol=1e-13).p
+    assert rel_l2(pg, exact) < 1e-9
+    assert abs(pg.mean()) < 1e-14 * np.abs(pg).max()
+    rr = np.linalg.norm(oracle.residual(ob, od - od.mean(), pg, wl.h)) / np.linalg.norm(od - od.mean())
+    assert rr <= 1.0001e-10
+    s.close()
+
+
+@pytest.mark.parametrize("make,n,precision", [
+    (W.sphere_workload, 32, "mixed"),
+    (W.drop_film_workload, 128, "fp64"),
+    (W.drop_film_workload, 128, "mixed"),
+    (W.drop_film_workload, 48, "fp64"),
+    (W.drop_film_workload, 48, "mixed"),
+])
+def test_solve_matches_converged_oracle(make, n, precision):
+    note(f"solve {make.__name__} n={n} {precision}")
+    wl = make(n)
+    gb, gd = gpu_inputs(wl)
+    ob, od = oracle_inputs(wl)
+    s = S.Solver(*gb, wl.h, precision=precision, zero_guess=True)
+    p, st = s.solve(gd, 1e-10)
+    pg = N(p)
+    exact = oracle.solve(ob, od, wl.h, tol=1e-13)
+    ref10 = oracle.solve(ob, od, wl.h, tol=1e-10)
+    err = rel_l2(pg, exact.p)
+    note(f"  cycles {st.cycles} (oracle {ref10.cycles}) rr {st.rel_res:.3e} rel err {err:.3e}")
+    assert st.rel_res <= 1e-10
+    assert err < 1e-9
+    rr = np.linalg.norm(oracle.residual(ob, od - od.mean(), pg, wl.h)) / np.linalg.norm(od - od.mean())
+    assert rr <= 1.0001e-10
+    if precision == "fp64":
+        assert st.cycles == ref10.cycles
+    else:
+        assert st.cycles <= ref10.cycles + 2
+    s.close()
+
+
+def test_solve_layered_exact_tridiagonal():
+    n = 64
+    dims = (n, n, n)
+    wl = W.layered_film_workload(dims, height=0.15)
+    f = wl.f_film[:, 0, 0]
+    rho = W.RHO_FILM * f + W.RHO_GAS * (1.0 - f)
+    g = np.random.default_rng(18).standard_normal(n)
+    rhs, p_ref = refs.layered_solve(dims, 1.0 / n, rho, 1, 2, g)
+    beta = refs.layered_beta(dims, rho)
+    for precision in ("fp64", "mixed"):
+        s = make_solver(beta, 1.0 / n, precision=precision, zero_guess=True)
+        p, st = s.solve(T(rhs), 1e-10)
+        assert rel_l2(N(p), p_ref) < 1e-9, precision
+        s.close()
+
+
+def test_solve_closed_form():
+    for n in (16, 64):
+        b, p_disc, _ = refs.closed_form(n)
+        beta = refs.constant_beta((n, n, n))
+        s = make_solver(beta, 1.0 / n, zero_guess=True)
+        p, st = s.solve(T(b), 1e-12)
+        assert max_rel(N(p), p_disc) < 1e-10
+        s.close()
+
+
+def test_warm_start_and_statuses():
+    wl = W.sphere_workload(16)
+    gb, gd = gpu_inputs(wl)
+    s = S.Solver(*gb, wl.h)
+    p, st = s.solve(gd, 1e-10)
+    # warm start from the converged solution: no cycle needed
+    p2, st2 = s.solve(gd, 1e-8, p=p.clone())
+    assert st2.cycles == 0
+    s.close()
+    s = S.Solver(*gb, wl.h, max_cycles=1, zero_guess=True)
+    _, st = s.solve(gd, 1e-10, check=False)
+    assert st.status == S.L.MG_ENOCONV and st.cycles == 1
+    bad = gd.clone()
+    bad[1, 2, 3] = float("nan")
+    _, st = s.solve(bad, 1e-10, check=False)
+    assert st.status == S.L.MG_ENONFINITE
+    with pytest.raises(S.MgError):
+        s.solve(gd, 0.0)
+    s.close()
+    bx = gb[0].clone()
+    bx[3, 3, 3] = -1.0
+    with pytest.raises(S.MgError) as ei:
+        S.Solver(bx, gb[1], gb[2], wl.h)
+    assert ei.value.status == S.L.MG_EINVAL and "face coefficient" in str(ei.value)
+
+
+# ---------------------------------------------------------------------------
+# adjoint and gradients
+# ---------------------------------------------------------------------------
+
+def test_adjoint_and_face_grad_match_oracle():
+    wl = W.drop_film_workload(32)
+    gb, gd = gpu_inputs(wl)
+    ob, od = oracle_inputs(wl)
+    w = W.loss_weights(wl.dims)
+    s = S.Solver(*gb, wl.h, zero_guess=True)
+    p, _ = s.solve(gd, 1e-12)
+    lam, _ = s.solve_adjoint(T(w), 1e-12)
+    gx, gy, gz = s.face_grad(lam, p)
+    p_o, lam_o, (ox, oy, oz) = oracle.gradients(ob, od, w, wl.h, tol=1e-13)
+    assert rel_l2(N(lam), lam_o) < 1e-10
+    for a, r in zip((gx, gy, gz), (ox, oy, oz)):
+        assert rel_l2(N(a), r) < 1e-9
+    # the fused face-gradient kernel on identical inputs
+    lam_n, p_n = N(lam), N(p)
+    for a, r in zip(s.face_grad(T(lam_n), T(p_n)), oracle.face_grad(lam_n, p_n, wl.h)):
+        np.testing.assert_allclose(N(a), r, rtol=1e-14, atol=1e-300)
+    s.close()

@@ -153,7 +153,8 @@ int mg_update(mg_ctx *c, const double *beta_x, const double *beta_y, const doubl
 /*
  * mg_solve -- p = zero-mean solution of L p = rhs - mean(rhs).
  *   rhs   device [nz][ny][nx]; not modified.
- *   p     device [nz][ny][nx]; in: initial guess (unless MG_FLAG_ZERO_GUESS), out: solution.
+ *   p     device [nz][ny][nx], 16-byte aligned; in: initial guess (unless
+ *         MG_FLAG_ZERO_GUESS), out: solution.
  *   tol   stop at the first cycle with ||r||_2 <= tol ||rhs - mean(rhs)||_2 (> 0).
  *   st    host, nullable: statistics.
  * Returns MG_OK, MG_ENOCONV (p holds the last iterate, mean removed),

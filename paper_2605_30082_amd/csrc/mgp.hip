@@ -14,6 +14,7 @@
 
 #include "mgp_kernels.hpp"
 #include "mgp_sweep.hpp"
+#include "mgp_resid.hpp"
 
 using namespace mgp;
 
@@ -21,6 +22,7 @@ namespace {
 
 constexpr int kMaxCoarseCells = 64;
 constexpr int kTimingPairs = 4096;
+constexpr int kMaxPartials = 16384;  // partial sums of one reduction (>= blocks of any launch)
 
 template <typename T>
 struct LevelBufs {
@@ -210,8 +212,15 @@ int residual_restrict(mg_ctx* c, int l, const T* b, const T* x, T* bc)
     Level& C = c->lev[l + 1];
     LevelBufs<T>& B = bufs<T>(L);
     TimedLaunch tl(c, l, MG_K_RESTRICT, (double)L.n * (5.0 + 1.0 / 8.0) * sizeof(T));
-    k_residual_restrict<T><<<grid_for(C.n), kBlock, 0, c->stream>>>(B.bx, B.by, B.bz, L.d, C.d,
-                                                                   (T)(1.0 / (L.h * L.h)), b, x, bc);
+    if (res_tiled_ok(L.d, sizeof(T))) {
+        const ResGeom g = res_geom(L.d);
+        k_resid<T, RES_RESTRICT><<<g.blocks, kResNT, 0, c->stream>>>(B.bx, B.by, B.bz, b, x, nullptr, L.d,
+                                                                      (T)(1.0 / (L.h * L.h)), g.zc, g.ntx, g.nty,
+                                                                      nullptr, nullptr, bc, nullptr);
+    } else {
+        k_residual_restrict<T><<<grid_for(C.n), kBlock, 0, c->stream>>>(B.bx, B.by, B.bz, L.d, C.d,
+                                                                       (T)(1.0 / (L.h * L.h)), b, x, bc);
+    }
     CHECK_LAUNCH(c);
     return MG_OK;
 }
@@ -282,8 +291,37 @@ int residual_norm_launch(mg_ctx* c, const double* b, const double* p, double* r_
 {
     Level& L = c->lev[0];
     TimedLaunch tl(c, 0, MG_K_NORM, (double)L.n * 5.0 * sizeof(double));
+    if (!r_out && res_tiled_ok(L.d, sizeof(double))) {
+        const ResGeom g = res_geom(L.d);
+        k_resid<double, RES_NORM><<<g.blocks, kResNT, 0, c->stream>>>(L.f64.bx, L.f64.by, L.f64.bz, b, p, nullptr,
+                                                                       L.d, 1.0 / (L.h * L.h), g.zc, g.ntx, g.nty,
+                                                                       nullptr, nullptr, nullptr, c->partials);
+        CHECK_LAUNCH(c);
+        return reduce_to(c, g.blocks, slot);
+    }
     k_residual_norm<<<kReduceBlocks, kBlock, 0, c->stream>>>(L.f64.bx, L.f64.by, L.f64.bz, L.d,
                                                              1.0 / (L.h * L.h), b, p, r_out, c->partials);
+    CHECK_LAUNCH(c);
+    return reduce_to(c, kReduceBlocks, slot);
+}
+
+// Mixed-precision outer step on the finest grid: p_out = p_in + e (e FP32, or
+// 0 when e is NULL), r32 = (float)(b0 - L p_out), scal[slot] = ||r||^2.
+int outer_update(mg_ctx* c, const double* p_in, const float* e, double* p_out, float* r32, int slot)
+{
+    Level& F = c->lev[0];
+    const double bytes = (double)F.n * (5 * 8 + (e ? 4 : 0) + 8 + 4);
+    TimedLaunch tl(c, 0, MG_K_OUTER, bytes);
+    if (res_tiled_ok(F.d, sizeof(double))) {
+        const ResGeom g = res_geom(F.d);
+        k_resid<double, RES_OUTER><<<g.blocks, kResNT, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, c->b0, p_in,
+                                                                        e, F.d, 1.0 / (F.h * F.h), g.zc, g.ntx,
+                                                                        g.nty, p_out, r32, nullptr, c->partials);
+        CHECK_LAUNCH(c);
+        return reduce_to(c, g.blocks, slot);
+    }
+    k_outer_update<<<kReduceBlocks, kBlock, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, F.d, 1.0 / (F.h * F.h),
+                                                            c->b0, p_in, e, e ? 0 : 1, p_out, r32, c->partials);
     CHECK_LAUNCH(c);
     return reduce_to(c, kReduceBlocks, slot);
 }
@@ -312,6 +350,10 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
     }
     if (!rhs || !p || rhs == p) {
         set_err(c, "rhs and p must be distinct non-NULL device pointers");
+        return MG_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(p) % 16 != 0) {
+        set_err(c, "p must be 16-byte aligned");
         return MG_EINVAL;
     }
     if (!(tol > 0.0) || !std::isfinite(tol)) {
@@ -392,15 +434,8 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
         float* r32 = F0.f32.b;
         // initial residual in FP64, cast to FP32
         if (zero_guess) TRY(fill<double>(c, cur, n, 0.0));
-        {
-            TimedLaunch tl(c, 0, MG_K_OUTER, (double)n * (6 * 8 + 4 + 8));
-            k_outer_update<<<kReduceBlocks, kBlock, 0, c->stream>>>(F0.f64.bx, F0.f64.by, F0.f64.bz, F0.d,
-                                                                    1.0 / (F0.h * F0.h), c->b0, cur, nullptr, 1,
-                                                                    other, r32, c->partials);
-            CHECK_LAUNCH(c);
-        }
+        TRY(outer_update(c, cur, nullptr, other, r32, 2));
         std::swap(cur, other);
-        TRY(reduce_to(c, kReduceBlocks, 2));
         TRY(fetch_scalars(c, 3));
         rr = std::sqrt(c->host_scal[2]) / bnorm;
         if (st) st->hist[0] = rr;
@@ -411,15 +446,8 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
             float* ex = F0.f32.x;
             float* et = F0.f32.t;
             TRY(vcycle<float>(c, 0, &ex, &et, r32, true));
-            {
-                TimedLaunch tl(c, 0, MG_K_OUTER, (double)n * (6 * 8 + 4 + 8 + 4));
-                k_outer_update<<<kReduceBlocks, kBlock, 0, c->stream>>>(F0.f64.bx, F0.f64.by, F0.f64.bz, F0.d,
-                                                                        1.0 / (F0.h * F0.h), c->b0, cur, ex, 0,
-                                                                        other, r32, c->partials);
-                CHECK_LAUNCH(c);
-            }
+            TRY(outer_update(c, cur, ex, other, r32, 2));
             std::swap(cur, other);
-            TRY(reduce_to(c, kReduceBlocks, 2));
             ++cycles;
             TRY(fetch_scalars(c, 3));
             rr = std::sqrt(c->host_scal[2]) / bnorm;
@@ -494,20 +522,20 @@ void carve(mg_ctx* c, Arena& a)
     c->G = a.take<double>(nc * nc);
     const long m = nc + 1;
     c->work = a.take<double>(std::max<long>(m * 2 * m, n0));
-    c->partials = a.take<double>(kReduceBlocks);
+    c->partials = a.take<double>(kMaxPartials);
     c->scal = a.take<double>(16);
     for (int l = 0; l < c->nlev; ++l) {
         Level& L = c->lev[l];
-        L.f64.bx = a.take<double>(L.n);
-        L.f64.by = a.take<double>(L.n);
-        L.f64.bz = a.take<double>(L.n);
+        L.f64.bx = a.take<double>(n_fx(L.d));
+        L.f64.by = a.take<double>(n_fy(L.d));
+        L.f64.bz = a.take<double>(n_fz(L.d));
         L.f64.x = a.take<double>(L.n);
         L.f64.t = a.take<double>(L.n);
         L.f64.b = a.take<double>(L.n);
         if (c->mixed) {
-            L.f32.bx = a.take<float>(L.n);
-            L.f32.by = a.take<float>(L.n);
-            L.f32.bz = a.take<float>(L.n);
+            L.f32.bx = a.take<float>(n_fx(L.d));
+            L.f32.by = a.take<float>(n_fy(L.d));
+            L.f32.bz = a.take<float>(n_fz(L.d));
             L.f32.x = a.take<float>(L.n);
             L.f32.t = a.take<float>(L.n);
             L.f32.b = a.take<float>(L.n);
@@ -525,16 +553,17 @@ int setup_impl(mg_ctx* c, const double* pbx, const double* pby, const double* pb
     for (int l = 1; l < c->nlev; ++l) {
         Level& A = c->lev[l - 1];
         Level& B = c->lev[l];
-        k_coarsen_faces<<<grid_for(B.n), kBlock, 0, c->stream>>>(A.f64.bx, A.f64.by, A.f64.bz, A.d, B.d,
-                                                                 B.f64.bx, B.f64.by, B.f64.bz);
+        const long nf = n_fx(B.d) + n_fy(B.d) + n_fz(B.d);
+        k_coarsen_faces<<<grid_for(nf), kBlock, 0, c->stream>>>(A.f64.bx, A.f64.by, A.f64.bz, A.d, B.d,
+                                                                B.f64.bx, B.f64.by, B.f64.bz);
         CHECK_LAUNCH(c);
     }
     if (c->mixed) {
         for (int l = 0; l < c->nlev; ++l) {
             Level& L = c->lev[l];
-            k_convert<double, float><<<grid_for(L.n), kBlock, 0, c->stream>>>(L.f64.bx, L.n, L.f32.bx);
-            k_convert<double, float><<<grid_for(L.n), kBlock, 0, c->stream>>>(L.f64.by, L.n, L.f32.by);
-            k_convert<double, float><<<grid_for(L.n), kBlock, 0, c->stream>>>(L.f64.bz, L.n, L.f32.bz);
+            k_convert<double, float><<<grid_for(n_fx(L.d)), kBlock, 0, c->stream>>>(L.f64.bx, n_fx(L.d), L.f32.bx);
+            k_convert<double, float><<<grid_for(n_fy(L.d)), kBlock, 0, c->stream>>>(L.f64.by, n_fy(L.d), L.f32.by);
+            k_convert<double, float><<<grid_for(n_fz(L.d)), kBlock, 0, c->stream>>>(L.f64.bz, n_fz(L.d), L.f32.bz);
             CHECK_LAUNCH(c);
         }
     }

@@ -1,0 +1,80 @@
+// Device helpers shared by the stencil kernels: 2-element vectors, buffer
+// loads, the LDS-only barrier and the reciprocal-based quotient.
+#pragma once
+
+#include "mgp_kernels.hpp"
+
+namespace mgp {
+
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+
+// LDS-only barrier: waits for this wave's LDS operations, then synchronises the
+// workgroup.  Outstanding global loads stay in flight (a full __syncthreads
+// would drain them).
+__device__ inline void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Quotient n/d from the hardware reciprocal: about 1 ulp in FP32; in FP64 the
+// reciprocal is refined by two Newton steps and the quotient by one residual
+// correction (within 1 ulp of the correctly rounded quotient).  d > 0 here.
+__device__ __forceinline__ float quot(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double quot(double n, double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    const double q = n * r;
+    return fma(fma(-d, q, n), r, q);
+}
+
+// Buffer loads: a loop-invariant resource per array (base, size in bytes), a
+// wave-uniform byte offset of the z-plane and a 32-bit lane byte offset.  A
+// lane offset at or beyond the resource size reads 0, so kOutside masks one
+// lane and a resource of size 0 masks a whole plane, without any per-load
+// vector instruction.  Every array of a level must stay below 2^31 bytes.
+constexpr unsigned kOutside = 0x80000000u;
+constexpr int kBufWord3 = 0x00020000;  // raw 32-bit data format, no swizzle
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3);
+}
+__device__ __forceinline__ float bload(float*, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ double bload(double*, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ typename Vec2<T>::type bload2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float2 bload2<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double2 bload2<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ T bload1(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return bload((T*)nullptr, r, voff, soff);
+}
+
+}  // namespace mgp

@@ -1,13 +1,14 @@
 // Device kernels of the multigrid pressure-Poisson solver (gfx950).
 //
-// Internal layout of a level with nx*ny*nz cells (x fastest):
-//   cell arrays          T[n]
-//   face coefficients    three T[n] arrays holding, per cell, the coefficient
-//                        of its LOW face in x, y and z.  The low face of a cell
-//                        on the low wall is stored as 0; the high face of a
-//                        cell is the low face of the next cell, or a wall.
-// Every stencil kernel therefore reads one coefficient per face and never
-// needs the (nx+1)-padded public layout.
+// Internal layouts of a level with nx*ny*nz cells (x fastest):
+//   cell arrays   T[nz][ny][nx]
+//   x-faces       T[nz][ny][nx+2]  entry x = face between cells x-1 and x;
+//                                  x = 0 and x = nx are walls (stored 0), x = nx+1
+//                                  is padding (0) that keeps rows of even length
+//   y-faces       T[nz][ny+1][nx]  rows 0 and ny are walls (0)
+//   z-faces       T[nz+1][ny][nx]  planes 0 and nz are walls (0)
+// Both faces of every cell are plain loads (walls are real zeros), so the
+// stencil kernels need no branch for a wall coefficient.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,6 +22,22 @@ constexpr int kReduceBlocks = 1024;  // fixed partial count -> deterministic red
 struct Dims {
     int nx, ny, nz;
 };
+
+__host__ __device__ inline long fx_index(const Dims& d, int x, int y, int z)
+{
+    return ((long)z * d.ny + y) * (d.nx + 2) + x;
+}
+__host__ __device__ inline long fy_index(const Dims& d, int x, int y, int z)
+{
+    return ((long)z * (d.ny + 1) + y) * d.nx + x;
+}
+__host__ __device__ inline long fz_index(const Dims& d, int x, int y, int z)
+{
+    return ((long)z * d.ny + y) * d.nx + x;
+}
+__host__ __device__ inline long n_fx(const Dims& d) { return (long)d.nz * d.ny * (d.nx + 2); }
+__host__ __device__ inline long n_fy(const Dims& d) { return (long)d.nz * (d.ny + 1) * d.nx; }
+__host__ __device__ inline long n_fz(const Dims& d) { return (long)(d.nz + 1) * d.ny * d.nx; }
 
 // ---------------------------------------------------------------------------
 // reductions: fixed-shape block partials, then one block sums them in order
@@ -124,80 +141,110 @@ __device__ inline bool bad_coeff(double v)
     return !(v > 0.0) || !(v < INFINITY);  // NaN, <= 0 or +Inf
 }
 
-// public face layouts -> internal low-face arrays; partial count of invalid interior entries
+// public face layouts -> internal layouts (walls and padding written as 0);
+// partial count of interior entries that are not finite and > 0
 __global__ void k_import_faces(const double* __restrict__ pbx, const double* __restrict__ pby,
                                const double* __restrict__ pbz, Dims d, double* __restrict__ bx,
                                double* __restrict__ by, double* __restrict__ bz,
                                double* __restrict__ partials)
 {
-    const long n = (long)d.nx * d.ny * d.nz;
+    const long nx_ = n_fx(d), ny_ = n_fy(d), nz_ = n_fz(d);
+    const long total = nx_ + ny_ + nz_;
     double bad = 0.0;
-    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
-        int i, j, k;
-        cell_of(c, d, i, j, k);
-        const long fx = ((long)k * d.ny + j) * (d.nx + 1) + i;
-        const long fy = ((long)k * (d.ny + 1) + j) * d.nx + i;
-        const long fz = c;  // z-face layout [nz+1][ny][nx]: low face of cell c has index c
-        double vx = 0.0, vy = 0.0, vz = 0.0;
-        if (i > 0) { vx = pbx[fx]; bad += bad_coeff(vx) ? 1.0 : 0.0; }
-        if (j > 0) { vy = pby[fy]; bad += bad_coeff(vy) ? 1.0 : 0.0; }
-        if (k > 0) { vz = pbz[fz]; bad += bad_coeff(vz) ? 1.0 : 0.0; }
-        bx[c] = vx;
-        by[c] = vy;
-        bz[c] = vz;
+    for (long f = (long)blockIdx.x * kBlock + threadIdx.x; f < total; f += (long)gridDim.x * kBlock) {
+        if (f < nx_) {
+            const int x = (int)(f % (d.nx + 2));
+            const long row = f / (d.nx + 2);
+            double v = 0.0;
+            if (x >= 1 && x <= d.nx - 1) {
+                v = pbx[row * (d.nx + 1) + x];
+                bad += bad_coeff(v) ? 1.0 : 0.0;
+            }
+            bx[f] = v;
+        } else if (f < nx_ + ny_) {
+            const long g = f - nx_;
+            const int y = (int)((g / d.nx) % (d.ny + 1));
+            double v = 0.0;
+            if (y >= 1 && y <= d.ny - 1) {
+                v = pby[g];
+                bad += bad_coeff(v) ? 1.0 : 0.0;
+            }
+            by[g] = v;
+        } else {
+            const long g = f - nx_ - ny_;
+            const int z = (int)(g / ((long)d.ny * d.nx));
+            double v = 0.0;
+            if (z >= 1 && z <= d.nz - 1) {
+                v = pbz[g];
+                bad += bad_coeff(v) ? 1.0 : 0.0;
+            }
+            bz[g] = v;
+        }
     }
     bad = block_sum(bad);
     if (threadIdx.x == 0) partials[blockIdx.x] = bad;
 }
 
-// internal low-face arrays of a level -> public face layouts (walls written as 0)
+// internal face layouts of a level -> public face layouts
 template <typename T>
 __global__ void k_export_faces(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
                                Dims d, double* __restrict__ pbx, double* __restrict__ pby,
                                double* __restrict__ pbz)
 {
     const long nfx = (long)d.nz * d.ny * (d.nx + 1);
-    const long nfy = (long)d.nz * (d.ny + 1) * d.nx;
-    const long nfz = (long)(d.nz + 1) * d.ny * d.nx;
+    const long nfy = n_fy(d), nfz = n_fz(d);
     const long total = nfx + nfy + nfz;
     for (long f = (long)blockIdx.x * kBlock + threadIdx.x; f < total; f += (long)gridDim.x * kBlock) {
         if (f < nfx) {
-            const int i = (int)(f % (d.nx + 1));
+            const int x = (int)(f % (d.nx + 1));
             const long row = f / (d.nx + 1);
-            pbx[f] = (i == 0 || i == d.nx) ? 0.0 : (double)bx[row * d.nx + i];
+            pbx[f] = (double)bx[row * (d.nx + 2) + x];
         } else if (f < nfx + nfy) {
-            const long g = f - nfx;
-            const int i = (int)(g % d.nx);
-            const long r = g / d.nx;
-            const int j = (int)(r % (d.ny + 1));
-            const int k = (int)(r / (d.ny + 1));
-            pby[g] = (j == 0 || j == d.ny) ? 0.0 : (double)by[((long)k * d.ny + j) * d.nx + i];
+            pby[f - nfx] = (double)by[f - nfx];
         } else {
-            const long g = f - nfx - nfy;
-            const int k = (int)(g / ((long)d.ny * d.nx));
-            pbz[g] = (k == 0 || k == d.nz) ? 0.0 : (double)bz[g];
+            pbz[f - nfx - nfy] = (double)bz[f - nfx - nfy];
         }
     }
 }
 
-// coarse low face = mean of the 4 fine low faces that tile it (wall faces stay 0)
+// coarse face = mean of the 4 fine faces that tile it (walls stay 0)
 __global__ void k_coarsen_faces(const double* __restrict__ fbx, const double* __restrict__ fby,
                                 const double* __restrict__ fbz, Dims f, Dims c, double* __restrict__ cbx,
                                 double* __restrict__ cby, double* __restrict__ cbz)
 {
-    const long n = (long)c.nx * c.ny * c.nz;
-    const long fs = (long)f.nx * f.ny;
-    for (long C = (long)blockIdx.x * kBlock + threadIdx.x; C < n; C += (long)gridDim.x * kBlock) {
-        int I, J, K;
-        cell_of(C, c, I, J, K);
-        const long f0 = (long)(2 * K) * fs + (long)(2 * J) * f.nx + 2 * I;  // fine cell (2I, 2J, 2K)
-        double vx = 0.0, vy = 0.0, vz = 0.0;
-        if (I > 0) vx = (fbx[f0] + fbx[f0 + f.nx] + fbx[f0 + fs] + fbx[f0 + fs + f.nx]) / 4.0;
-        if (J > 0) vy = (fby[f0] + fby[f0 + 1] + fby[f0 + fs] + fby[f0 + fs + 1]) / 4.0;
-        if (K > 0) vz = (fbz[f0] + fbz[f0 + 1] + fbz[f0 + f.nx] + fbz[f0 + f.nx + 1]) / 4.0;
-        cbx[C] = vx;
-        cby[C] = vy;
-        cbz[C] = vz;
+    const long nx_ = n_fx(c), ny_ = n_fy(c), nz_ = n_fz(c);
+    const long total = nx_ + ny_ + nz_;
+    for (long g = (long)blockIdx.x * kBlock + threadIdx.x; g < total; g += (long)gridDim.x * kBlock) {
+        if (g < nx_) {
+            const int X = (int)(g % (c.nx + 2));
+            const long row = g / (c.nx + 2);
+            const int Y = (int)(row % c.ny), Z = (int)(row / c.ny);
+            double v = 0.0;
+            if (X >= 1 && X <= c.nx - 1)
+                v = (fbx[fx_index(f, 2 * X, 2 * Y, 2 * Z)] + fbx[fx_index(f, 2 * X, 2 * Y + 1, 2 * Z)] +
+                     fbx[fx_index(f, 2 * X, 2 * Y, 2 * Z + 1)] + fbx[fx_index(f, 2 * X, 2 * Y + 1, 2 * Z + 1)]) / 4.0;
+            cbx[g] = v;
+        } else if (g < nx_ + ny_) {
+            const long h = g - nx_;
+            const int X = (int)(h % c.nx);
+            const long row = h / c.nx;
+            const int Y = (int)(row % (c.ny + 1)), Z = (int)(row / (c.ny + 1));
+            double v = 0.0;
+            if (Y >= 1 && Y <= c.ny - 1)
+                v = (fby[fy_index(f, 2 * X, 2 * Y, 2 * Z)] + fby[fy_index(f, 2 * X + 1, 2 * Y, 2 * Z)] +
+                     fby[fy_index(f, 2 * X, 2 * Y, 2 * Z + 1)] + fby[fy_index(f, 2 * X + 1, 2 * Y, 2 * Z + 1)]) / 4.0;
+            cby[h] = v;
+        } else {
+            const long h = g - nx_ - ny_;
+            const int X = (int)(h % c.nx);
+            const long row = h / c.nx;
+            const int Y = (int)(row % c.ny), Z = (int)(row / c.ny);
+            double v = 0.0;
+            if (Z >= 1 && Z <= c.nz - 1)
+                v = (fbz[fz_index(f, 2 * X, 2 * Y, 2 * Z)] + fbz[fz_index(f, 2 * X + 1, 2 * Y, 2 * Z)] +
+                     fbz[fz_index(f, 2 * X, 2 * Y + 1, 2 * Z)] + fbz[fz_index(f, 2 * X + 1, 2 * Y + 1, 2 * Z)]) / 4.0;
+            cbz[h] = v;
+        }
     }
 }
 
@@ -231,12 +278,12 @@ __global__ void k_coarse_inverse(const double* __restrict__ bx, const double* __
         const int i = c % d.nx, j = (c / d.nx) % d.ny, k = c / (d.nx * d.ny);
         const int sy = d.nx, sz = d.nx * d.ny;
         double diag = 0.0, bf;
-        if (i > 0)        { bf = bx[c];      row[c - 1] += bf / h2;  diag -= bf / h2; }
-        if (i < d.nx - 1) { bf = bx[c + 1];  row[c + 1] += bf / h2;  diag -= bf / h2; }
-        if (j > 0)        { bf = by[c];      row[c - sy] += bf / h2; diag -= bf / h2; }
-        if (j < d.ny - 1) { bf = by[c + sy]; row[c + sy] += bf / h2; diag -= bf / h2; }
-        if (k > 0)        { bf = bz[c];      row[c - sz] += bf / h2; diag -= bf / h2; }
-        if (k < d.nz - 1) { bf = bz[c + sz]; row[c + sz] += bf / h2; diag -= bf / h2; }
+        if (i > 0)        { bf = bx[fx_index(d, i, j, k)];     row[c - 1] += bf / h2;  diag -= bf / h2; }
+        if (i < d.nx - 1) { bf = bx[fx_index(d, i + 1, j, k)]; row[c + 1] += bf / h2;  diag -= bf / h2; }
+        if (j > 0)        { bf = by[fy_index(d, i, j, k)];     row[c - sy] += bf / h2; diag -= bf / h2; }
+        if (j < d.ny - 1) { bf = by[fy_index(d, i, j + 1, k)]; row[c + sy] += bf / h2; diag -= bf / h2; }
+        if (k > 0)        { bf = bz[fz_index(d, i, j, k)];     row[c - sz] += bf / h2; diag -= bf / h2; }
+        if (k < d.nz - 1) { bf = bz[fz_index(d, i, j, k + 1)]; row[c + sz] += bf / h2; diag -= bf / h2; }
         row[c] += diag;
         row[n] = 1.0;
     }
@@ -312,12 +359,12 @@ __device__ inline void stencil(const T* __restrict__ bx, const T* __restrict__ b
 {
     const long sy = d.nx, sz = (long)d.nx * d.ny;
     T dg = 0, of = 0, f;
-    if (i > 0)        { f = bx[c];      dg += f; of += f * (T)x[c - 1]; }
-    if (i < d.nx - 1) { f = bx[c + 1];  dg += f; of += f * (T)x[c + 1]; }
-    if (j > 0)        { f = by[c];      dg += f; of += f * (T)x[c - sy]; }
-    if (j < d.ny - 1) { f = by[c + sy]; dg += f; of += f * (T)x[c + sy]; }
-    if (k > 0)        { f = bz[c];      dg += f; of += f * (T)x[c - sz]; }
-    if (k < d.nz - 1) { f = bz[c + sz]; dg += f; of += f * (T)x[c + sz]; }
+    if (i > 0)        { f = bx[fx_index(d, i, j, k)];     dg += f; of += f * (T)x[c - 1]; }
+    if (i < d.nx - 1) { f = bx[fx_index(d, i + 1, j, k)]; dg += f; of += f * (T)x[c + 1]; }
+    if (j > 0)        { f = by[fy_index(d, i, j, k)];     dg += f; of += f * (T)x[c - sy]; }
+    if (j < d.ny - 1) { f = by[fy_index(d, i, j + 1, k)]; dg += f; of += f * (T)x[c + sy]; }
+    if (k > 0)        { f = bz[fz_index(d, i, j, k)];     dg += f; of += f * (T)x[c - sz]; }
+    if (k < d.nz - 1) { f = bz[fz_index(d, i, j, k + 1)]; dg += f; of += f * (T)x[c + sz]; }
     diag = dg;
     off = of;
 }
@@ -381,14 +428,13 @@ __global__ void k_half_sweep(const T* __restrict__ bx, const T* __restrict__ by,
     const long c = ((long)k * d.ny + j) * d.nx + i;
     T dg, of;
     if (zero_src) {
-        const long sy = d.nx, sz = (long)d.nx * d.ny;
         dg = 0;
-        if (i > 0) dg += bx[c];
-        if (i < d.nx - 1) dg += bx[c + 1];
-        if (j > 0) dg += by[c];
-        if (j < d.ny - 1) dg += by[c + sy];
-        if (k > 0) dg += bz[c];
-        if (k < d.nz - 1) dg += bz[c + sz];
+        if (i > 0) dg += bx[fx_index(d, i, j, k)];
+        if (i < d.nx - 1) dg += bx[fx_index(d, i + 1, j, k)];
+        if (j > 0) dg += by[fy_index(d, i, j, k)];
+        if (j < d.ny - 1) dg += by[fy_index(d, i, j + 1, k)];
+        if (k > 0) dg += bz[fz_index(d, i, j, k)];
+        if (k < d.nz - 1) dg += bz[fz_index(d, i, j, k + 1)];
         of = 0;
     } else {
         stencil(bx, by, bz, src, d, i, j, k, c, dg, of);
@@ -469,12 +515,12 @@ __global__ void k_outer_update(const double* __restrict__ bx, const double* __re
         cell_of(c, d, i, j, k);
         auto Q = [&](long t) { return zero_e ? p_in[t] : p_in[t] + (double)e[t]; };
         double dg = 0.0, of = 0.0, f;
-        if (i > 0)        { f = bx[c];      dg += f; of += f * Q(c - 1); }
-        if (i < d.nx - 1) { f = bx[c + 1];  dg += f; of += f * Q(c + 1); }
-        if (j > 0)        { f = by[c];      dg += f; of += f * Q(c - sy); }
-        if (j < d.ny - 1) { f = by[c + sy]; dg += f; of += f * Q(c + sy); }
-        if (k > 0)        { f = bz[c];      dg += f; of += f * Q(c - sz); }
-        if (k < d.nz - 1) { f = bz[c + sz]; dg += f; of += f * Q(c + sz); }
+        if (i > 0)        { f = bx[fx_index(d, i, j, k)];     dg += f; of += f * Q(c - 1); }
+        if (i < d.nx - 1) { f = bx[fx_index(d, i + 1, j, k)]; dg += f; of += f * Q(c + 1); }
+        if (j > 0)        { f = by[fy_index(d, i, j, k)];     dg += f; of += f * Q(c - sy); }
+        if (j < d.ny - 1) { f = by[fy_index(d, i, j + 1, k)]; dg += f; of += f * Q(c + sy); }
+        if (k > 0)        { f = bz[fz_index(d, i, j, k)];     dg += f; of += f * Q(c - sz); }
+        if (k < d.nz - 1) { f = bz[fz_index(d, i, j, k + 1)]; dg += f; of += f * Q(c + sz); }
         const double qc = Q(c);
         const double r = b[c] - (of - dg * qc) * inv_h2;
         p_out[c] = qc;

@@ -33,6 +33,17 @@ if ROOT not in sys.path:
 METRIC = "time-to-1e-10 residual & smoother HBM GB/s at 512³, FP64 vs FP32+refinement"
 HBM_PEAK_GBPS = 8000.0
 KERNEL_NAMES = ["sweep", "residual_restrict", "prolong_correct", "outer_update", "residual_norm"]
+# kernel symbol timed for each class (one per class and precision), as rocprofv3 names it
+KERNEL_SYMBOLS = {
+    ("sweep", "mixed"): "mgp::k_sweep_fused<float, 8>",
+    ("sweep", "fp64"): "mgp::k_sweep_fused<double, 16>",
+    ("residual_restrict", "mixed"): "mgp::k_resid<float, 1>",
+    ("residual_restrict", "fp64"): "mgp::k_resid<double, 1>",
+    ("prolong_correct", "mixed"): "mgp::k_prolong_tiled<float>",
+    ("prolong_correct", "fp64"): "mgp::k_prolong_tiled<double>",
+    ("outer_update", "mixed"): "mgp::k_resid<double, 2>",
+    ("residual_norm", "fp64"): "mgp::k_resid<double, 0>",
+}
 
 
 def log(msg: str) -> None:
@@ -53,16 +64,24 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_summary(stats_list):
-    """Sum the per-kernel-class event timings (finest grid) over several solves."""
+def kernel_summary(stats_list, precision):
+    """Per kernel class: HIP-event timings summed over several solves, for all
+    launches of the class's kernel (every level) and for the finest grid alone."""
     out = {}
     for k, name in enumerate(KERNEL_NAMES):
         ms = sum(s.kernel_ms[k] for s in stats_list)
         n = sum(s.kernel_launches[k] for s in stats_list)
         by = sum(s.kernel_bytes[k] for s in stats_list)
+        ms0 = sum(s.kernel_ms_finest[k] for s in stats_list)
+        n0 = sum(s.kernel_launches_finest[k] for s in stats_list)
+        by0 = sum(s.kernel_bytes_finest[k] for s in stats_list)
         if n:
-            out[name] = {"ms_total": ms, "launches": n, "avg_ms": ms / n, "alg_bytes_per_launch": by / n,
-                         "achieved_gbps": by / (ms * 1e-3) / 1e9 if ms > 0 else None}
+            out[name] = {"kernel": KERNEL_SYMBOLS.get((name, precision)),
+                         "ms_total": ms, "launches": n, "avg_ms": ms / n, "alg_bytes_per_launch": by / n,
+                         "achieved_gbps": by / (ms * 1e-3) / 1e9 if ms > 0 else None,
+                         "finest": {"launches": n0, "avg_ms": ms0 / n0 if n0 else None,
+                                    "alg_bytes_per_launch": by0 / n0 if n0 else None,
+                                    "achieved_gbps": by0 / (ms0 * 1e-3) / 1e9 if ms0 > 0 else None}}
     return out
 
 
@@ -143,7 +162,7 @@ def main() -> int:
     mixed_ms = statistics.median(phases["solve"])
     mixed_cycles = solve_stats[-1].cycles
     mixed_rr = max(s.rel_res for s in solve_stats)
-    ksum = kernel_summary(solve_stats + [r[2] for r in recs])
+    ksum = kernel_summary(solve_stats + [r[2] for r in recs], "mixed")
     dominant = max(ksum, key=lambda k: ksum[k]["ms_total"]) if ksum else None
 
     # plain FP64 solve on the same input, same tolerance
@@ -161,24 +180,29 @@ def main() -> int:
                 torch.cuda.synchronize()
                 times.append(e0.elapsed_time(e1))
                 st64.append(st)
-            ks64 = kernel_summary(st64)
+            ks64 = kernel_summary(st64, "fp64")
             sw = ks64.get("sweep", {})
+            sw0 = sw.get("finest", {})
             fp64 = {"time_to_tol_ms": statistics.median(times), "cycles": st64[-1].cycles,
                     "rel_res": st64[-1].rel_res, "kernels": ks64,
-                    "smoother_gbps": sw.get("achieved_gbps"),
-                    "smoother_cell_updates_per_s": (cells / (sw["avg_ms"] * 1e-3)) if sw else None}
+                    "smoother_gbps_finest": sw0.get("achieved_gbps"),
+                    "smoother_cell_updates_per_s": (cells / (sw0["avg_ms"] * 1e-3)) if sw0.get("avg_ms") else None}
             diff = float(torch.linalg.vector_norm(p - p64) / torch.linalg.vector_norm(p64))
             fp64["mixed_vs_fp64_rel_l2"] = diff
             del p64
         log(f"fp64 solve {fp64['time_to_tol_ms']:.2f} ms, {fp64['cycles']} cycles")
 
     sweep = ksum.get("sweep", {})
+    sweep0 = sweep.get("finest", {})
     roofline = None
     if dominant:
         d = ksum[dominant]
-        roofline = {"bound": "hbm", "kernel": dominant, "achieved": d["achieved_gbps"], "peak": HBM_PEAK_GBPS,
-                    "unit": "GB/s", "frac": d["achieved_gbps"] / HBM_PEAK_GBPS if d["achieved_gbps"] else None,
-                    "traffic": None, "avg_launch_ms": d["avg_ms"], "alg_bytes_per_launch": d["alg_bytes_per_launch"]}
+        roofline = {"bound": "hbm", "kernel": d["kernel"], "class": dominant, "achieved": d["achieved_gbps"],
+                    "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": d["achieved_gbps"] / HBM_PEAK_GBPS if d["achieved_gbps"] else None,
+                    "traffic": None, "avg_launch_ms": d["avg_ms"], "launches": d["launches"],
+                    "alg_bytes_per_launch": d["alg_bytes_per_launch"],
+                    "finest": d["finest"]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -201,8 +225,8 @@ def main() -> int:
                    "n": n, "cells": cells, "levels": mixed.num_levels, "precision": "mixed (FP32 V-cycle, FP64 outer)",
                    "pre_post_sweeps": [2, 2], "tol": args.tol},
         "mixed": {"time_to_tol_ms": mixed_ms, "cycles": mixed_cycles, "rel_res_max": mixed_rr,
-                  "smoother_gbps": sweep.get("achieved_gbps"),
-                  "smoother_cell_updates_per_s": (cells / (sweep["avg_ms"] * 1e-3)) if sweep else None,
+                  "smoother_gbps_finest": sweep0.get("achieved_gbps"),
+                  "smoother_cell_updates_per_s": (cells / (sweep0["avg_ms"] * 1e-3)) if sweep0.get("avg_ms") else None,
                   "kernels": ksum},
         "fp64": fp64,
         "phases_ms": {k: statistics.median(v) for k, v in phases.items()},

@@ -95,7 +95,7 @@ typedef struct {
 #define MG_HIST_MAX 256
 #define MG_MAX_LEVELS 16
 
-/* kernel classes timed under MG_FLAG_TIMING (finest grid only) */
+/* kernel classes timed under MG_FLAG_TIMING */
 enum {
     MG_K_SWEEP = 0,      /* red-black Gauss-Seidel sweep kernel */
     MG_K_RESTRICT = 1,   /* fused residual + restriction */
@@ -113,10 +113,15 @@ typedef struct {
     double setup_ms;            /* wall time of mg_setup */
     double solve_ms;            /* wall time of this solve (host clock, stream synchronised) */
     double hist[MG_HIST_MAX];   /* rel_res before cycle 1 (hist[0]) and after each cycle */
-    /* MG_FLAG_TIMING only: per kernel class, finest grid */
+    /* MG_FLAG_TIMING only: per kernel class, launches of the class's tiled
+     * kernel (one kernel per class and precision) on every level ... */
     double kernel_ms[MG_K_COUNT];        /* summed HIP-event durations */
     long long kernel_launches[MG_K_COUNT];
     double kernel_bytes[MG_K_COUNT];     /* summed algorithmic HBM bytes of those launches */
+    /* ... and the same totals for the finest grid alone */
+    double kernel_ms_finest[MG_K_COUNT];
+    long long kernel_launches_finest[MG_K_COUNT];
+    double kernel_bytes_finest[MG_K_COUNT];
 } mg_stats;
 
 /*

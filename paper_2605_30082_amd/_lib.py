@@ -37,7 +37,10 @@ class MgStats(ctypes.Structure):
                 ("solve_ms", ctypes.c_double), ("hist", ctypes.c_double * MG_HIST_MAX),
                 ("kernel_ms", ctypes.c_double * MG_K_COUNT),
                 ("kernel_launches", ctypes.c_longlong * MG_K_COUNT),
-                ("kernel_bytes", ctypes.c_double * MG_K_COUNT)]
+                ("kernel_bytes", ctypes.c_double * MG_K_COUNT),
+                ("kernel_ms_finest", ctypes.c_double * MG_K_COUNT),
+                ("kernel_launches_finest", ctypes.c_longlong * MG_K_COUNT),
+                ("kernel_bytes_finest", ctypes.c_double * MG_K_COUNT)]
 
 
 _D = ctypes.c_void_p       # device pointer

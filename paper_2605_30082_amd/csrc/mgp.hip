@@ -15,6 +15,7 @@
 #include "mgp_kernels.hpp"
 #include "mgp_sweep.hpp"
 #include "mgp_resid.hpp"
+#include "mgp_transfer.hpp"
 
 using namespace mgp;
 
@@ -61,11 +62,12 @@ struct mg_ctx {
     // timing
     hipEvent_t* ev = nullptr;
     int ev_class[kTimingPairs];
+    int ev_level[kTimingPairs];
     double ev_bytes[kTimingPairs];
     int ev_used = 0;
-    double kms[MG_K_COUNT];
-    long long klaunch[MG_K_COUNT];
-    double kbytes[MG_K_COUNT];
+    double kms[MG_K_COUNT], kms0[MG_K_COUNT];
+    long long klaunch[MG_K_COUNT], klaunch0[MG_K_COUNT];
+    double kbytes[MG_K_COUNT], kbytes0[MG_K_COUNT];
     char err[512];
 };
 
@@ -129,15 +131,19 @@ double now_ms()
 
 // --- timing ---------------------------------------------------------------
 
+// Brackets one launch with HIP events when the context times kernels.  Only
+// the tiled kernels are timed (one kernel name per class and precision), on
+// every level; the finest level is also totalled on its own.
 struct TimedLaunch {
     mg_ctx* c;
     int cls;
     bool on;
-    TimedLaunch(mg_ctx* ctx, int level, int k, double bytes) : c(ctx), cls(k), on(false)
+    TimedLaunch(mg_ctx* ctx, int level, int k, double bytes, bool tiled = true) : c(ctx), cls(k), on(false)
     {
-        if (!c->ev || level != 0 || c->ev_used >= kTimingPairs) return;
+        if (!c->ev || !tiled || c->ev_used >= kTimingPairs) return;
         on = true;
         c->ev_class[c->ev_used] = k;
+        c->ev_level[c->ev_used] = level;
         c->ev_bytes[c->ev_used] = bytes;
         (void)hipEventRecord(c->ev[2 * c->ev_used], c->stream);
     }
@@ -155,9 +161,15 @@ void harvest(mg_ctx* c)
     for (int t = 0; t < c->ev_used; ++t) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->ev[2 * t], c->ev[2 * t + 1]) == hipSuccess) {
-            c->kms[c->ev_class[t]] += ms;
-            c->klaunch[c->ev_class[t]] += 1;
-            c->kbytes[c->ev_class[t]] += c->ev_bytes[t];
+            const int k = c->ev_class[t];
+            c->kms[k] += ms;
+            c->klaunch[k] += 1;
+            c->kbytes[k] += c->ev_bytes[t];
+            if (c->ev_level[t] == 0) {
+                c->kms0[k] += ms;
+                c->klaunch0[k] += 1;
+                c->kbytes0[k] += c->ev_bytes[t];
+            }
         }
     }
     c->ev_used = 0;
@@ -195,7 +207,7 @@ int sweep(mg_ctx* c, int l, const T* b, const T* in, T* out, int order, bool zer
     Level& L = c->lev[l];
     LevelBufs<T>& B = bufs<T>(L);
     const double bytes = (double)L.n * sweep_bytes_per_cell<T>();
-    TimedLaunch tl(c, l, MG_K_SWEEP, bytes);
+    TimedLaunch tl(c, l, MG_K_SWEEP, bytes, sweep_is_fused(L.d, sizeof(T)));
     const hipError_t e = launch_sweep<T>(B.bx, B.by, B.bz, L.d, (T)(L.h * L.h), b, in, out, order,
                                          zero_in, c->stream);
     if (e != hipSuccess) {
@@ -211,8 +223,9 @@ int residual_restrict(mg_ctx* c, int l, const T* b, const T* x, T* bc)
     Level& L = c->lev[l];
     Level& C = c->lev[l + 1];
     LevelBufs<T>& B = bufs<T>(L);
-    TimedLaunch tl(c, l, MG_K_RESTRICT, (double)L.n * (5.0 + 1.0 / 8.0) * sizeof(T));
-    if (res_tiled_ok(L.d, sizeof(T))) {
+    const bool tiled = res_tiled_ok(L.d, sizeof(T));
+    TimedLaunch tl(c, l, MG_K_RESTRICT, (double)L.n * (5.0 + 1.0 / 8.0) * sizeof(T), tiled);
+    if (tiled) {
         const ResGeom g = res_geom(L.d);
         k_resid<T, RES_RESTRICT><<<g.blocks, kResNT, 0, c->stream>>>(B.bx, B.by, B.bz, b, x, nullptr, L.d,
                                                                       (T)(1.0 / (L.h * L.h)), g.zc, g.ntx, g.nty,
@@ -230,8 +243,14 @@ int prolong_correct(mg_ctx* c, int l, const T* e, T* x)
 {
     Level& L = c->lev[l];
     Level& C = c->lev[l + 1];
-    TimedLaunch tl(c, l, MG_K_PROLONG, (double)L.n * (2.0 + 1.0 / 8.0) * sizeof(T));
-    k_prolong_correct<T><<<grid_for(L.n), kBlock, 0, c->stream>>>(L.d, C.d, e, x);
+    const bool tiled = pro_tiled_ok(L.d, sizeof(T));
+    TimedLaunch tl(c, l, MG_K_PROLONG, (double)L.n * (2.0 + 1.0 / 8.0) * sizeof(T), tiled);
+    if (tiled) {
+        const ProGeom g = pro_geom(L.d, C.d);
+        k_prolong_tiled<T><<<g.blocks, kProNT, 0, c->stream>>>(L.d, C.d, e, x, g.kc, g.ntx, g.nty);
+    } else {
+        k_prolong_correct<T><<<grid_for(L.n), kBlock, 0, c->stream>>>(L.d, C.d, e, x);
+    }
     CHECK_LAUNCH(c);
     return MG_OK;
 }
@@ -290,8 +309,9 @@ int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init)
 int residual_norm_launch(mg_ctx* c, const double* b, const double* p, double* r_out, int slot)
 {
     Level& L = c->lev[0];
-    TimedLaunch tl(c, 0, MG_K_NORM, (double)L.n * 5.0 * sizeof(double));
-    if (!r_out && res_tiled_ok(L.d, sizeof(double))) {
+    const bool tiled = !r_out && res_tiled_ok(L.d, sizeof(double));
+    TimedLaunch tl(c, 0, MG_K_NORM, (double)L.n * 5.0 * sizeof(double), tiled);
+    if (tiled) {
         const ResGeom g = res_geom(L.d);
         k_resid<double, RES_NORM><<<g.blocks, kResNT, 0, c->stream>>>(L.f64.bx, L.f64.by, L.f64.bz, b, p, nullptr,
                                                                        L.d, 1.0 / (L.h * L.h), g.zc, g.ntx, g.nty,
@@ -311,8 +331,9 @@ int outer_update(mg_ctx* c, const double* p_in, const float* e, double* p_out, f
 {
     Level& F = c->lev[0];
     const double bytes = (double)F.n * (5 * 8 + (e ? 4 : 0) + 8 + 4);
-    TimedLaunch tl(c, 0, MG_K_OUTER, bytes);
-    if (res_tiled_ok(F.d, sizeof(double))) {
+    const bool tiled = res_tiled_ok(F.d, sizeof(double));
+    TimedLaunch tl(c, 0, MG_K_OUTER, bytes, tiled);
+    if (tiled) {
         const ResGeom g = res_geom(F.d);
         k_resid<double, RES_OUTER><<<g.blocks, kResNT, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, c->b0, p_in,
                                                                         e, F.d, 1.0 / (F.h * F.h), g.zc, g.ntx,
@@ -361,9 +382,9 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
         return MG_EINVAL;
     }
     for (int k = 0; k < MG_K_COUNT; ++k) {
-        c->kms[k] = 0;
-        c->klaunch[k] = 0;
-        c->kbytes[k] = 0;
+        c->kms[k] = c->kms0[k] = 0;
+        c->klaunch[k] = c->klaunch0[k] = 0;
+        c->kbytes[k] = c->kbytes0[k] = 0;
     }
     c->ev_used = 0;
     Level& F = c->lev[0];
@@ -480,6 +501,9 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
             st->kernel_ms[k] = c->kms[k];
             st->kernel_launches[k] = c->klaunch[k];
             st->kernel_bytes[k] = c->kbytes[k];
+            st->kernel_ms_finest[k] = c->kms0[k];
+            st->kernel_launches_finest[k] = c->klaunch0[k];
+            st->kernel_bytes_finest[k] = c->kbytes0[k];
         }
     }
     return status;

@@ -277,13 +277,18 @@ hipError_t launch_fused(const T* bx, const T* by, const T* bz, Dims d, T h2, con
 // Grids at least 64 cells wide use the fused single-pass kernel (FP32 with
 // 64 x 8 tiles; FP64 with 64 x 16 tiles, which halve the ring share at its
 // lower occupancy); smaller ones run the two half-sweeps as two launches.
+inline bool sweep_is_fused(const Dims& d, size_t elem)
+{
+    const long big = n_fx(d) > n_fz(d) ? n_fx(d) : n_fz(d);
+    return d.nx >= 64 && (d.nx % 2) == 0 && d.ny >= 8 && big * (long)elem < (1L << 31);
+}
+
 template <typename T>
 hipError_t launch_sweep(const T* bx, const T* by, const T* bz, Dims d, T h2, const T* b, const T* in, T* out,
                         int order, bool zero_in, hipStream_t s)
 {
     const int c0 = order == 0 ? 0 : 1;
-    const long big = n_fx(d) > n_fz(d) ? n_fx(d) : n_fz(d);
-    if (d.nx >= 64 && (d.nx % 2) == 0 && d.ny >= 8 && big * (long)sizeof(T) < (1L << 31)) {
+    if (sweep_is_fused(d, sizeof(T))) {
         if constexpr (sizeof(T) == 8) return launch_fused<T, 16>(bx, by, bz, d, h2, b, in, out, c0, zero_in, s);
         else return launch_fused<T, 8>(bx, by, bz, d, h2, b, in, out, c0, zero_in, s);
     }

@@ -53,12 +53,16 @@ class SolveStats:
     kernel_ms: List[float] = field(default_factory=list)
     kernel_launches: List[int] = field(default_factory=list)
     kernel_bytes: List[float] = field(default_factory=list)
+    kernel_ms_finest: List[float] = field(default_factory=list)
+    kernel_launches_finest: List[int] = field(default_factory=list)
+    kernel_bytes_finest: List[float] = field(default_factory=list)
 
     @classmethod
     def from_c(cls, s: L.MgStats) -> "SolveStats":
         n = min(s.cycles + 1, L.MG_HIST_MAX)
         return cls(s.status, s.cycles, s.rel_res, s.rhs_mean_removed, s.setup_ms, s.solve_ms,
-                   list(s.hist[:n]), list(s.kernel_ms), list(s.kernel_launches), list(s.kernel_bytes))
+                   list(s.hist[:n]), list(s.kernel_ms), list(s.kernel_launches), list(s.kernel_bytes),
+                   list(s.kernel_ms_finest), list(s.kernel_launches_finest), list(s.kernel_bytes_finest))
 
 
 def plan_levels(dims: Sequence[int], coarse_max: int = 4) -> int:

@@ -1,0 +1,141 @@
+"""The differentiable solve (torch.autograd.Function over the C ABI) against
+independent references: dense bordered solves at 8^3 and central finite
+differences of oracle solves at 32^3.
+
+Loss = sum(w p).  Gradient tolerance for finite differences (the FD noise floor
+makes a purely relative test wrong for tiny entries):
+    |fd - adj| <= 1e-4 |adj| + 1e-7 max|g|.
+The loss is linear in the right-hand side, so its differences take a unit step:
+the solve's residual error is then not amplified by 1/eps.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import refs
+from gpu_util import N, T, gpu_inputs, note, oracle_inputs, rel_l2
+from paper_2605_30082_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+S = pytest.importorskip("paper_2605_30082_amd.solver")
+from paper_2605_30082_amd.autograd import poisson_solve  # noqa: E402
+
+
+def leaf(t):
+    return t.detach().clone().requires_grad_(True)
+
+
+def zero_walls(beta):
+    bx, by, bz = (a.copy() for a in beta)
+    bx[:, :, 0] = bx[:, :, -1] = 0.0
+    by[:, 0, :] = by[:, -1, :] = 0.0
+    bz[0] = bz[-1] = 0.0
+    return bx, by, bz
+
+
+def autograd_grads(wl, w, precision="fp64", tol=1e-12, save_p=False):
+    gb, gd = gpu_inputs(wl)
+    rhs, bx, by, bz = leaf(gd), leaf(gb[0]), leaf(gb[1]), leaf(gb[2])
+    p = poisson_solve(rhs, bx, by, bz, wl.h, tol=tol, precision=precision, save_p=save_p)
+    loss = (T(w) * p).sum()
+    loss.backward()
+    return N(p), N(rhs.grad), (N(bx.grad), N(by.grad), N(bz.grad))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gradients_match_dense_reference_8cubed(precision):
+    wl = W.drop_film_workload(8)
+    w = W.loss_weights(wl.dims)
+    p, g_rhs, g_beta = autograd_grads(wl, w, precision=precision)
+    ob, od = oracle_inputs(wl)
+    zb = zero_walls(ob)
+    p_ref = refs.dense_solve(zb, od - od.mean(), wl.h)
+    lam_ref = refs.dense_solve(zb, w - w.mean(), wl.h)
+    G, masks = refs.gradient_matrix(wl.dims)
+    gf_ref = (G @ lam_ref.ravel()) * (G @ p_ref.ravel()) / wl.h ** 2
+    assert rel_l2(p, p_ref) < 1e-9
+    assert rel_l2(g_rhs, lam_ref) < 1e-9
+    got = refs.interior_faces(g_beta, masks)
+    assert rel_l2(got, gf_ref) < 1e-8
+    for a, m in zip(g_beta, masks):
+        assert np.all(a[~m] == 0.0)
+
+
+def test_gradients_match_oracle_finite_differences_32cubed():
+    wl = W.drop_film_workload(32)
+    w = W.loss_weights(wl.dims)
+    p, g_rhs, g_beta = autograd_grads(wl, w, tol=1e-12)
+    ob, od = oracle_inputs(wl)
+    h = wl.h
+    p0 = oracle.solve(ob, od, h, tol=1e-13).p
+    eps = 1e-6
+
+    def loss(beta, rhs):
+        return float(np.sum(w * oracle.solve(beta, rhs, h, tol=1e-13, p0=p0).p))
+
+    # 32 entries on faces across a density jump, 32 uniform among interior faces
+    rho = oracle.density(wl.f_drop, wl.f_film, wl.rho_drop, wl.rho_film, wl.rho_gas)
+    cand_jump, cand_all = [], []
+    nz, ny, nx = rho.shape
+    for axis in range(3):
+        shape = ob[axis].shape
+        k, j, i = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+        coord = (i, j, k)[axis]
+        interior = (coord > 0) & (coord < (nx, ny, nz)[axis])
+        if axis == 0:
+            d = np.zeros(shape); d[:, :, 1:nx] = np.abs(np.diff(rho, axis=2))
+        elif axis == 1:
+            d = np.zeros(shape); d[:, 1:ny, :] = np.abs(np.diff(rho, axis=1))
+        else:
+            d = np.zeros(shape); d[1:nz] = np.abs(np.diff(rho, axis=0))
+        for idx in zip(*np.nonzero(interior & (d > 1.0))):
+            cand_jump.append((axis, idx))
+        for idx in zip(*np.nonzero(interior)):
+            cand_all.append((axis, idx))
+    g = np.random.default_rng(3)
+    picks = [cand_jump[t] for t in g.choice(len(cand_jump), 32, replace=False)]
+    picks += [cand_all[t] for t in g.choice(len(cand_all), 32, replace=False)]
+    gmax = max(np.abs(a).max() for a in g_beta)
+    worst = 0.0
+    for axis, idx in picks:
+        bp = [a.copy() for a in ob]
+        bm = [a.copy() for a in ob]
+        bp[axis][idx] += eps
+        bm[axis][idx] -= eps
+        fd = (loss(bp, od) - loss(bm, od)) / (2 * eps)
+        adj = g_beta[axis][idx]
+        err = abs(fd - adj) / (1e-4 * abs(adj) + 1e-7 * gmax)
+        worst = max(worst, err)
+        assert err <= 1.0, (axis, idx, fd, adj)
+    # rhs entries (linear direction: unit step)
+    lmax = np.abs(g_rhs).max()
+    for t in g.choice(od.size, 8, replace=False):
+        idx = np.unravel_index(t, od.shape)
+        rp, rm = od.copy(), od.copy()
+        rp[idx] += 1.0
+        rm[idx] -= 1.0
+        fd = (loss(ob, rp) - loss(ob, rm)) / 2.0
+        assert abs(fd - g_rhs[idx]) <= 1e-4 * abs(g_rhs[idx]) + 1e-7 * lmax
+    note(f"FD check: worst normalised error {worst:.3f}")
+
+
+def test_save_p_and_partial_requires_grad():
+    wl = W.drop_film_workload(16)
+    w = W.loss_weights(wl.dims)
+    _, g1, gb1 = autograd_grads(wl, w, save_p=False)
+    _, g2, gb2 = autograd_grads(wl, w, save_p=True)
+    assert rel_l2(g2, g1) < 1e-10
+    for a, b in zip(gb2, gb1):
+        assert rel_l2(a, b) < 1e-9
+    # only the rhs requires a gradient: backward runs the adjoint solve alone
+    gb, gd = gpu_inputs(wl)
+    rhs = leaf(gd)
+    p = poisson_solve(rhs, gb[0], gb[1], gb[2], wl.h, tol=1e-12)
+    (T(w) * p).sum().backward()
+    assert rel_l2(N(rhs.grad), g1) < 1e-10
+    # the solution does not depend on the rhs mean
+    rhs2 = leaf(gd + 3.0)
+    p2 = poisson_solve(rhs2, gb[0], gb[1], gb[2], wl.h, tol=1e-12)
+    assert rel_l2(N(p2), N(p)) < 1e-10

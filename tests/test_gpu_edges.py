@@ -1,0 +1,111 @@
+"""Edge cases of the GPU solver against the oracle: degenerate and single-level
+grids, ragged and anisotropic grids, warm starts, coefficient updates, and the
+argument checks of the Python front end."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import N, T, dev, gpu_inputs, note, oracle_inputs, rel_l2
+from paper_2605_30082_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+S = pytest.importorskip("paper_2605_30082_amd.solver")
+
+
+def random_beta(dims, seed):
+    nx, ny, nz = dims
+    g = np.random.default_rng(seed)
+    return (g.uniform(1e-3, 0.9, (nz, ny, nx + 1)), g.uniform(1e-3, 0.9, (nz, ny + 1, nx)),
+            g.uniform(1e-3, 0.9, (nz + 1, ny, nx)))
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 1), (1, 3, 2), (4, 4, 4), (3, 3, 3), (8, 8, 8),
+                                  (96, 96, 96), (128, 64, 32), (16, 32, 64), (64, 64, 16)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_on_unusual_grids(dims, precision):
+    nx, ny, nz = dims
+    beta = random_beta(dims, 31)
+    h = 1.0 / max(dims)
+    rhs = np.random.default_rng(32).standard_normal((nz, ny, nx))
+    s = S.Solver(T(beta[0]), T(beta[1]), T(beta[2]), h, precision=precision, zero_guess=True)
+    p, st = s.solve(T(rhs), 1e-10)
+    pg = N(p)
+    ref = oracle.solve(beta, rhs, h, tol=1e-13)
+    note(f"{dims} {precision}: levels {s.num_levels} cycles {st.cycles} (oracle {ref.cycles})")
+    if rhs.size == 1:
+        assert st.cycles == 0 and np.all(pg == 0)
+    else:
+        assert st.rel_res <= 1e-10
+        assert rel_l2(pg, ref.p) < 1e-9
+    s.close()
+
+
+def test_warm_start_matches_oracle_lockstep():
+    wl = W.drop_film_workload(32)
+    gb, gd = gpu_inputs(wl)
+    ob, od = oracle_inputs(wl)
+    p0 = np.random.default_rng(33).standard_normal(od.shape)
+    s = S.Solver(*gb, wl.h, max_cycles=3)
+    p, st = s.solve(gd, 1e-14, p=T(p0), check=False)
+    ref = oracle.solve(ob, od, wl.h, tol=1e-14, max_cycles=3, p0=p0, check=False)
+    assert st.status == S.L.MG_ENOCONV and ref.status == oracle.OR_ENOCONV
+    np.testing.assert_allclose(st.hist, ref.hist, rtol=1e-8)
+    assert rel_l2(N(p), ref.p) < 1e-11
+    s.close()
+
+
+def test_update_equals_fresh_setup():
+    a = W.drop_film_workload(64)
+    b = W.sphere_workload(64)
+    ga, gda = gpu_inputs(a)
+    gbb, gdb = gpu_inputs(b)
+    s = S.Solver(*ga, a.h, precision="mixed", zero_guess=True)
+    s.update(*gbb)
+    p1, st1 = s.solve(gdb, 1e-10)
+    s2 = S.Solver(*gbb, b.h, precision="mixed", zero_guess=True)
+    p2, st2 = s2.solve(gdb, 1e-10)
+    assert st1.cycles == st2.cycles
+    assert torch.equal(p1, p2)
+    # a rejected update leaves the context unusable until the next good update
+    bad = gbb[0].clone()
+    bad[5, 5, 5] = float("nan")
+    with pytest.raises(S.MgError):
+        s.update(bad, gbb[1], gbb[2])
+    with pytest.raises(S.MgError):
+        s.solve(gdb, 1e-10)
+    s.update(*ga)
+    p3, _ = s.solve(gda, 1e-10)
+    assert torch.isfinite(p3).all()
+    s.close()
+    s2.close()
+
+
+def test_misaligned_p_is_rejected():
+    wl = W.sphere_workload(8)
+    gb, gd = gpu_inputs(wl)
+    s = S.Solver(*gb, wl.h)
+    buf = torch.zeros(8 * 8 * 8 + 1, dtype=torch.float64, device=dev())
+    p = buf[1:].view(8, 8, 8)
+    with pytest.raises(S.MgError) as ei:
+        s.solve(gd, 1e-10, p=p)
+    assert "aligned" in str(ei.value)
+    s.close()
+
+
+def test_front_end_argument_checks():
+    wl = W.sphere_workload(8)
+    gb, gd = gpu_inputs(wl)
+    with pytest.raises(TypeError):
+        S.Solver(gb[0].float(), gb[1], gb[2], wl.h)
+    with pytest.raises(ValueError):
+        S.Solver(gb[0].cpu(), gb[1], gb[2], wl.h)
+    with pytest.raises(S.MgError):
+        S.Solver(*gb, wl.h, precision="half")
+    with pytest.raises(S.MgError):
+        S.Solver(*gb, wl.h, bc="dirichlet")
+    s = S.Solver(*gb, wl.h)
+    with pytest.raises(ValueError):
+        s.solve(gd[:4].contiguous(), 1e-10)
+    s.close()

@@ -45,6 +45,37 @@ KERNEL_SYMBOLS = {
     ("residual_norm", "fp64"): "mgp::k_resid<double, 0>",
 }
 
+# HBM bytes per dispatch of the FP32 smoother on the 512^3 film + 32 drops workload
+# (average over all levels, the unit of the roofline figure), from two rocprofv3 PMC
+# passes over one step: FETCH_SIZE and WRITE_SIZE in KiB, scaled by what the same
+# counters read for a plain 1 GiB device copy (x2.0 and x1.0 on this part).  Valid
+# only for the kernel sources they were taken on: the hash below is recomputed at
+# run time and the figure is dropped (null) once the sources differ.
+TRAFFIC = {
+    "kernel": "mgp::k_sweep_fused<float, 8>",
+    "n": 512,
+    "sources": ["mgp_sweep.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp"],
+    "sha256": "d7d7dcde9e9067df71e389b25bc1eb570be4ee6c6360ce9ecb602469a5d23ac4",
+    "fetch_kib": 481623.6275390625,
+    "write_kib": 149760.0,
+    "fetch_scale": 2.0,
+    "write_scale": 1.0,
+}
+
+
+def measured_traffic(kernel: str, n: int):
+    """Scaled HBM bytes per dispatch for `kernel`, or None when no counters match it."""
+    import hashlib
+    if kernel != TRAFFIC["kernel"] or n != TRAFFIC["n"]:
+        return None
+    h = hashlib.sha256()
+    for name in TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_2605_30082_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != TRAFFIC["sha256"]:
+        return None
+    return (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]) * 1024.0
+
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -61,6 +92,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solves")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: all available)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (scales PMC byte counters)")
     return ap.parse_args()
 
 
@@ -85,6 +118,21 @@ def kernel_summary(stats_list, precision):
     return out
 
 
+def copy_calibration() -> int:
+    """A plain device copy of known size: FETCH_SIZE / WRITE_SIZE of its dispatches give
+    the factors that turn those counters into HBM bytes on this part."""
+    import torch
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": True, "bytes_read_per_copy": x.nbytes,
+                      "bytes_written_per_copy": y.nbytes, "copies": 5}), flush=True)
+    return 0
+
+
 def main() -> int:
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -92,6 +140,8 @@ def main() -> int:
         print(json.dumps({"error": "single-GPU solver: --gpus must be 1 (no multi-GPU path is built)",
                           "n_gpus": args.gpus}), flush=True)
         return 2
+    if args.copy_calibration:
+        return copy_calibration()
 
     import numpy as np
     import torch
@@ -200,7 +250,9 @@ def main() -> int:
         roofline = {"bound": "hbm", "kernel": d["kernel"], "class": dominant, "achieved": d["achieved_gbps"],
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": d["achieved_gbps"] / HBM_PEAK_GBPS if d["achieved_gbps"] else None,
-                    "traffic": None, "avg_launch_ms": d["avg_ms"], "launches": d["launches"],
+                    "traffic": measured_traffic(d["kernel"], n), "traffic_unit": "HBM bytes per launch",
+                    "avg_launch_ms": d["avg_ms"],
+                    "launches": d["launches"],
                     "alg_bytes_per_launch": d["alg_bytes_per_launch"],
                     "finest": d["finest"]}
 

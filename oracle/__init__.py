@@ -64,6 +64,7 @@ def lib():
             "or_face_coeffs": (None, [dp, I, I, I, dp, dp, dp]),
             "or_divergence": (None, [dp, dp, dp, I, I, I, D, D, dp]),
             "or_velocity_correct": (None, [dp, dp, dp, I, I, I, D, D, dp, dp, dp, dp]),
+            "or_vof_grad": (I, [dp, dp, I, I, I, D, D, D, dp, dp, dp, dp, dp]),
             "or_apply": (None, [dp, dp, dp, I, I, I, D, dp, dp]),
             "or_residual": (None, [dp, dp, dp, I, I, I, D, dp, dp, dp]),
             "or_rbgs_half": (None, [dp, dp, dp, I, I, I, D, dp, dp, I]),
@@ -152,6 +153,20 @@ def velocity_correct(beta, p, u, v, w, h: float, dt: float = 1.0):
     lib().or_velocity_correct(_p(bx), _p(by), _p(bz), nx, ny, nz, h, dt, _p(p),
                               _p(u2), _p(v2), _p(w2))
     return u2, v2, w2
+
+
+def vof_grad(f_drop, f_film, rho_drop: float, rho_film: float, rho_gas: float, g_beta):
+    """(dL/df_drop, dL/df_film) from dL/dbeta (face layouts), by the chain rule
+    through the mixture density and the harmonic-mean face coefficients."""
+    fd, ff = _c(f_drop), _c(f_film)
+    gx, gy, gz = (_c(a) for a in g_beta)
+    nx, ny, nz = _dims(fd)
+    gd, gf = np.empty_like(fd), np.empty_like(fd)
+    st = lib().or_vof_grad(_p(fd), _p(ff), nx, ny, nz, rho_drop, rho_film, rho_gas,
+                           _p(gx), _p(gy), _p(gz), _p(gd), _p(gf))
+    if st != OR_OK:
+        raise MemoryError("or_vof_grad")
+    return gd, gf
 
 
 # ---------------------------------------------------------------------------

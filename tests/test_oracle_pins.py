@@ -482,6 +482,58 @@ def test_face_gradient_matches_matrix_calculus(oracle_mod):
         assert np.all(a[~m] == 0)
 
 
+
+def test_vof_gradient_two_cells_closed_form(oracle_mod):
+    # one interior face between cells 0 and 1: J = w * 2 / (rho0 + rho1)
+    fd = np.array([[[0.3, 0.6]]])
+    ff = np.array([[[0.5, 0.7]]])        # cell 1: 0.6 + 0.7 > 1, gas clamped to 0
+    rd, rf, rg = 1000.0, 960.0, 1.2
+    w = 0.7
+    gx = np.array([[[0.0, w, 0.0]]])
+    gy = np.zeros((1, 2, 2))
+    gz = np.zeros((2, 1, 2))
+    gd, gf = oracle_mod.vof_grad(fd, ff, rd, rf, rg, (gx, gy, gz))
+    rho0 = rd * 0.3 + rf * 0.5 + rg * 0.2
+    rho1 = rd * 0.6 + rf * 0.7
+    dj = -2.0 * w / (rho0 + rho1) ** 2
+    np.testing.assert_allclose(gd.ravel(), [dj * (rd - rg), dj * rd], rtol=1e-14)
+    np.testing.assert_allclose(gf.ravel(), [dj * (rf - rg), dj * rf], rtol=1e-14)
+
+
+def test_vof_gradient_matches_finite_differences(oracle_mod):
+    # J(f) = sum_f w_f beta_f(f) on a ragged grid; cells with and without gas
+    dims = (5, 4, 3)
+    nx, ny, nz = dims
+    g = rng(17)
+    fd = g.uniform(0.0, 0.7, (nz, ny, nx))
+    ff = g.uniform(0.0, 0.7, (nz, ny, nx))
+    rd, rf, rg = 1000.0, 960.0, 1.2
+    w = [g.standard_normal(s) for s in ((nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx))]
+
+    def J(a, b):
+        beta = oracle_mod.faces_from_vof(a, b, rd, rf, rg)
+        return sum(float(np.sum(x * y)) for x, y in zip(w, beta))
+
+    gd, gf = oracle_mod.vof_grad(fd, ff, rd, rf, rg, w)
+    gmax = max(np.abs(gd).max(), np.abs(gf).max())
+    eps = 1e-6
+    checked = 0
+    for c in range(fd.size):
+        idx = np.unravel_index(c, fd.shape)
+        gas = 1.0 - fd[idx] - ff[idx]
+        if abs(gas) < 10 * eps:
+            continue                      # the clamp's kink: no derivative
+        for f, grad in ((fd, gd), (ff, gf)):
+            fp, fm = f.copy(), f.copy()
+            fp[idx] += eps
+            fm[idx] -= eps
+            a = (J(fp, ff), J(fm, ff)) if f is fd else (J(fd, fp), J(fd, fm))
+            fdiff = (a[0] - a[1]) / (2 * eps)
+            # FD noise ~1e-6 relative; a wrong term, sign or factor is O(1) off
+            assert abs(fdiff - grad[idx]) <= 1e-5 * abs(grad[idx]) + 1e-9 * gmax, (idx, fdiff, grad[idx])
+            checked += 1
+    assert checked >= 100
+
 # ---------------------------------------------------------------------------
 # host logic and failure paths
 # ---------------------------------------------------------------------------

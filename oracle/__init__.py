@@ -75,6 +75,7 @@ def lib():
             "or_face_grad": (None, [dp, dp, I, I, I, D, dp, dp, dp]),
             "or_num_levels": (I, [I, I, I, I]),
             "or_solve": (I, [dp, dp, dp, I, I, I, D, dp, dp, D, I, I, I, I, dp, ip, dp, dp]),
+            "or_fcg_solve": (I, [dp, dp, dp, I, I, I, D, dp, dp, D, I, I, I, I, dp, ip, dp, dp]),
             "or_vcycles": (I, [dp, dp, dp, I, I, I, D, dp, dp, I, I, I, I]),
         }
         for name, (res, args) in sig.items():
@@ -286,6 +287,27 @@ def solve(beta, rhs, h: float, tol: float = 1e-10, max_cycles: int = 100, pre: i
     if check and st != OR_OK:
         raise RuntimeError(f"or_solve failed with status {st} (rr={rr.value})")
     return OracleResult(st, p, cyc.value, rr.value, hist[: cyc.value + 1].copy(), mu.value)
+
+
+def fcg_solve(beta, rhs, h: float, tol: float = 1e-10, max_iters: int = 100, pre: int = 2,
+              post: int = 2, coarse_max: int = 4, p0: Optional[np.ndarray] = None,
+              check: bool = True) -> OracleResult:
+    """Zero-mean p with L p = rhs - mean(rhs), by flexible CG preconditioned with one
+    V-cycle per iteration; `cycles` of the result counts iterations."""
+    bx, by, bz = (_c(a) for a in beta)
+    rhs = _c(rhs)
+    nx, ny, nz = _dims(rhs)
+    p = np.zeros_like(rhs) if p0 is None else _c(p0).copy()
+    hist = np.zeros(max_iters + 1)
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    mu = ctypes.c_double(0.0)
+    st = lib().or_fcg_solve(_p(bx), _p(by), _p(bz), nx, ny, nz, h, _p(rhs), _p(p), tol, max_iters,
+                            pre, post, coarse_max, _p(hist), ctypes.byref(it), ctypes.byref(rr),
+                            ctypes.byref(mu))
+    if check and st != OR_OK:
+        raise RuntimeError(f"or_fcg_solve failed with status {st} (rr={rr.value})")
+    return OracleResult(st, p, it.value, rr.value, hist[: it.value + 1].copy(), mu.value)
 
 
 def vcycles(beta, rhs, h: float, cycles: int, p0: Optional[np.ndarray] = None, pre: int = 2,

@@ -654,6 +654,100 @@ int or_solve(const double *bx, const double *by, const double *bz, int nx, int n
     return st;
 }
 
+static double dot(const double *x, const double *y, long n)
+{
+    double s = 0.0;
+    long c;
+    for (c = 0; c < n; c++) s += x[c] * y[c];
+    return s;
+}
+
+/* Flexible conjugate gradients with one V-cycle (from a zero guess) as the
+ * preconditioner B; the variant keeps one previous search direction (Notay's
+ * flexible CG truncated to one direction), which stays valid when B is not
+ * exactly symmetric (the V-cycle's restriction is not a multiple of the
+ * prolongation's transpose).  With r = b - L x, per iteration:
+ *   z = B r
+ *   d = z - ((z, q_prev) / (d_prev, q_prev)) d_prev     (d = z at the start)
+ *   q = L d,  alpha = (d, r) / (d, q),  x += alpha d,  r -= alpha q
+ * The system is the negative semi-definite L p = b - mean(b); the signs of
+ * L and B cancel in alpha and in the direction update.  Stops at the first
+ * iteration with ||r|| <= tol ||b - mean b|| (r is the updated residual).
+ * Arguments and results as or_solve, with iterations in place of cycles. */
+int or_fcg_solve(const double *bx, const double *by, const double *bz, int nx, int ny, int nz,
+                 double h, const double *rhs, double *p, double tol, int max_iters,
+                 int pre, int post, int coarse_max,
+                 double *hist, int *iters, double *rel_res, double *rhs_mean)
+{
+    or_hier H;
+    long n = (long)nx * ny * nz, c;
+    int st, it = 0, have_prev = 0;
+    double mu, bnorm, rr, dq_prev = 0.0;
+    double *b, *x, *r, *z, *d, *q;
+    if (tol <= 0.0 || max_iters < 0 || pre < 0 || post < 0) return OR_EINVAL;
+    st = build_hier(&H, bx, by, bz, nx, ny, nz, h, coarse_max);
+    if (st != OR_OK) return st;
+    or_level *F = &H.lev[0];
+    b = malloc(sizeof(double) * 6 * (size_t)n);
+    if (!b) { free_hier(&H); return OR_ENOMEM; }
+    x = b + n; r = x + n; z = r + n; d = z + n; q = d + n;
+    mu = mean(rhs, n);
+    for (c = 0; c < n; c++) { b[c] = rhs[c] - mu; x[c] = p[c]; }
+    if (rhs_mean) *rhs_mean = mu;
+    bnorm = norm2(b, n);
+    if (!isfinite(bnorm)) { free(b); free_hier(&H); return OR_ENONFINITE; }
+    if (bnorm == 0.0) {
+        for (c = 0; c < n; c++) p[c] = 0.0;
+        if (hist) hist[0] = 0.0;
+        if (iters) *iters = 0;
+        if (rel_res) *rel_res = 0.0;
+        free(b);
+        free_hier(&H);
+        return OR_OK;
+    }
+    or_residual(F->bx, F->by, F->bz, nx, ny, nz, h, b, x, r);
+    rr = norm2(r, n) / bnorm;
+    if (hist) hist[0] = rr;
+    st = rr <= tol ? OR_OK : OR_ENOCONV;
+    while (st == OR_ENOCONV && it < max_iters) {
+        double alpha, dqv;
+        int vs;
+        /* z = B r: one V-cycle on L z = r from z = 0 */
+        memcpy(F->b, r, sizeof(double) * (size_t)n);
+        memset(F->x, 0, sizeof(double) * (size_t)n);
+        vs = vcycle(&H, 0, pre, post);
+        if (vs != OR_OK) { st = vs; break; }
+        memcpy(z, F->x, sizeof(double) * (size_t)n);
+        if (have_prev) {
+            double gamma = dot(z, q, n) / dq_prev;
+            for (c = 0; c < n; c++) d[c] = z[c] - gamma * d[c];
+        } else {
+            memcpy(d, z, sizeof(double) * (size_t)n);
+        }
+        or_apply(F->bx, F->by, F->bz, nx, ny, nz, h, d, q);
+        dqv = dot(d, q, n);
+        alpha = dot(d, r, n) / dqv;
+        for (c = 0; c < n; c++) {
+            x[c] += alpha * d[c];
+            r[c] -= alpha * q[c];
+        }
+        dq_prev = dqv;
+        have_prev = 1;
+        it++;
+        rr = norm2(r, n) / bnorm;
+        if (hist) hist[it] = rr;
+        if (!isfinite(rr)) { st = OR_ENONFINITE; break; }
+        if (rr <= tol) st = OR_OK;
+    }
+    mu = mean(x, n);
+    for (c = 0; c < n; c++) p[c] = x[c] - mu;
+    if (iters) *iters = it;
+    if (rel_res) *rel_res = rr;
+    free(b);
+    free_hier(&H);
+    return st;
+}
+
 /* Run exactly `cycles` V-cycles from the guess p on the projected rhs without a
  * stopping test and without removing the mean of p (used for lock-step
  * comparison of single cycles). */

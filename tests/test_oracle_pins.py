@@ -377,6 +377,55 @@ def test_solve_density_jump_matches_sparse_direct(oracle_mod, make):
     assert refs.rel_l2(res.p, ref) < 1e-11
 
 
+
+# flexible CG preconditioned by one V-cycle: the same exact discrete solutions
+@pytest.mark.parametrize("make", [W.sphere_workload, W.drop_film_workload])
+def test_fcg_density_jump_matches_dense_brute_force(oracle_mod, make):
+    wl = make(8)
+    beta, b = workload_inputs(oracle_mod, wl)
+    res = oracle_mod.fcg_solve(beta, b, wl.h, tol=1e-13)
+    ref = refs.dense_solve(zero_walls(beta), b - b.mean(), wl.h)
+    assert refs.rel_l2(res.p, ref) < 1e-11
+
+
+def test_fcg_matches_sparse_direct_and_needs_fewer_iterations(oracle_mod):
+    wl = W.drop_film_workload(16)
+    beta, b = workload_inputs(oracle_mod, wl)
+    res = oracle_mod.fcg_solve(beta, b, wl.h, tol=1e-10)
+    ref = refs.sparse_direct_solve(beta, b, wl.h)
+    vc = oracle_mod.solve(beta, b, wl.h, tol=1e-10)
+    assert res.rel_res <= 1e-10 and refs.rel_l2(res.p, ref) < 1e-9
+    # the updated residual is the true one up to rounding
+    true = np.linalg.norm(oracle_mod.residual(beta, b - b.mean(), res.p, wl.h)) / np.linalg.norm(b - b.mean())
+    assert abs(true - res.rel_res) <= 1e-3 * res.rel_res
+    assert res.cycles < vc.cycles
+    # residual history decreases monotonically enough to stop
+    assert np.all(np.diff(np.log(res.hist)) < 0)
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_fcg_layered_density_matches_tridiagonal(oracle_mod, n):
+    dims = (n, n, n)
+    wl = W.layered_film_workload(dims, height=0.15)
+    f = wl.f_film[:, 0, 0]
+    rho_layers = W.RHO_FILM * f + W.RHO_GAS * (1.0 - f)
+    g = rng(18).standard_normal(n)
+    rhs, p_ref = refs.layered_solve(dims, 1.0 / n, rho_layers, 1, 2, g)
+    beta = refs.layered_beta(dims, rho_layers)
+    res = oracle_mod.fcg_solve(beta, rhs, 1.0 / n, tol=1e-13)
+    assert refs.rel_l2(res.p, p_ref) < 1e-10
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16), (32, 16, 8)])
+def test_fcg_constant_coefficient_matches_dct(oracle_mod, dims):
+    nx, ny, nz = dims
+    h = 1.0 / nx
+    rhs = rng(19).standard_normal((nz, ny, nx))
+    beta = refs.constant_beta(dims, 0.8)
+    res = oracle_mod.fcg_solve(beta, rhs, h, tol=1e-13)
+    ref = refs.dct_solve(rhs - rhs.mean(), h, beta0=0.8)
+    assert refs.rel_l2(res.p, ref) < 1e-11
+
 def test_solve_at_tolerance_1e10_is_within_1e9_of_exact(oracle_mod):
     wl = W.sphere_workload(16)
     beta, b = workload_inputs(oracle_mod, wl)

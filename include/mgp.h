@@ -72,8 +72,14 @@ enum { MG_PREC_FP64 = 0, MG_PREC_MIXED = 1 };     /* V-cycle arithmetic */
 enum {
     MG_FLAG_ZERO_GUESS = 1,  /* mg_solve/mg_solve_adjoint ignore the initial contents of p
                                 (lambda) and start from zero */
-    MG_FLAG_TIMING = 2       /* time every launch of the finest-grid kernels with HIP events
+    MG_FLAG_TIMING = 2,      /* time every launch of the finest-grid kernels with HIP events
                                 and report the totals in mg_stats */
+    MG_FLAG_FCG = 4          /* solve by flexible conjugate gradients with one V-cycle (of
+                                the context's precision) as the preconditioner, one previous
+                                direction kept; mg_stats.cycles then counts iterations.
+                                Costs three more FP64 cell arrays.  The plain V-cycle
+                                iteration (flag clear) is the method of the paper's solver;
+                                this is a Krylov acceleration of it. */
 };
 
 /*
@@ -97,12 +103,13 @@ typedef struct {
 
 /* kernel classes timed under MG_FLAG_TIMING */
 enum {
-    MG_K_SWEEP = 0,      /* red-black Gauss-Seidel sweep kernel */
+    MG_K_SWEEP = 0,      /* red-black Gauss-Seidel sweep kernel (one sweep per launch) */
     MG_K_RESTRICT = 1,   /* fused residual + restriction */
     MG_K_PROLONG = 2,    /* fused prolongation + correction */
     MG_K_OUTER = 3,      /* FP64 update + residual + cast (mixed) */
     MG_K_NORM = 4,       /* residual norm */
-    MG_K_COUNT = 5
+    MG_K_SWEEP2 = 5,     /* two red-black sweeps per launch (FP32 smoothing pairs) */
+    MG_K_COUNT = 6
 };
 
 typedef struct {
@@ -217,6 +224,40 @@ int mg_faces_from_vof(const double *f_drop, const double *f_film, const int dims
 int mg_divergence(const double *u, const double *v, const double *w, const int dims[3],
                   double h, double dt, double *b, void *hip_stream);
 
+/*
+ * mg_vof_grad -- gradient of a loss with respect to the VOF fractions, given
+ * its gradient with respect to the face coefficients (e.g. from
+ * mg_face_grad): the chain rule through mg_faces_from_vof,
+ *   d beta_f / d rho_L = d beta_f / d rho_R = -2 / (rho_L + rho_R)^2,
+ *   d rho / d f_drop = rho_drop - rho_gas, d rho / d f_film = rho_film - rho_gas
+ * (rho_gas dropped in cells whose gas fraction is clamped, 1 - f_drop - f_film < 0).
+ *   f_drop, f_film   device cell arrays (the forward's inputs).
+ *   g_x, g_y, g_z    device face arrays (public layouts); wall entries ignored.
+ *   g_drop, g_film   device cell arrays (written).
+ *   dims host int[3]; densities > 0.  MG_EINVAL on bad arguments.
+ */
+int mg_vof_grad(const double *f_drop, const double *f_film, const int dims[3],
+                double rho_drop, double rho_film, double rho_gas,
+                const double *g_x, const double *g_y, const double *g_z,
+                double *g_drop, double *g_film, void *hip_stream);
+
+/*
+ * mg_velocity_correct -- the projection after the solve: the pressure-gradient
+ * term of the momentum equation applied over one step so that the velocity
+ * meets the continuity equation (Sec. 2).  On every interior face
+ *   u_f <- u_f - dt beta_f (p_R - p_L) / h
+ * with beta_f = 1/rho_face, the coefficients the solve used; wall faces are
+ * left untouched.  Then div_h u_new = div_h u - dt L p = dt (b - L p) for
+ * b = div_h u / dt: divergence-free to the solve's residual.
+ *   beta_x/y/z  device face arrays (public layouts), read only.
+ *   p           device cell array.
+ *   u, v, w     device face arrays, updated in place.
+ *   dims host int[3]; h > 0, dt > 0.  MG_EINVAL on bad arguments.
+ */
+int mg_velocity_correct(const double *beta_x, const double *beta_y, const double *beta_z, const double *p,
+                        const int dims[3], double h, double dt, double *u, double *v, double *w,
+                        void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Single-kernel entry points on one level of a context, for verification.
  * Level 0 is the finest grid; mg_level_info gives each level's dims and h.
@@ -235,7 +276,9 @@ int mg_level_info(const mg_ctx *c, int level, int dims[3], double *h);
 int mg_level_faces(mg_ctx *c, int level, double *beta_x, double *beta_y, double *beta_z);
 
 /* nsweeps full red-black Gauss-Seidel sweeps on level `level`:
- * order 0 = (red, black) per sweep, 1 = (black, red).  p in/out. */
+ * order 0 = (red, black) per sweep, 1 = (black, red).  p in/out.
+ * Sweeps run as in a V-cycle: in FP32 on grids at least 64 x 16 cells in
+ * (x, y), pairs of sweeps go through the two-sweeps-per-pass kernel. */
 int mg_smooth(mg_ctx *c, int level, int precision, const double *b, double *p,
               int nsweeps, int order);
 

@@ -15,10 +15,10 @@ LIB_PATH = os.path.join(PKG, "libmgp.so")
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EHIP, MG_ENOCONV, MG_ENONFINITE = 0, -1, -2, -3, -4, -5
 MG_BC_NEUMANN = 0
 MG_PREC_FP64, MG_PREC_MIXED = 0, 1
-MG_FLAG_ZERO_GUESS, MG_FLAG_TIMING = 1, 2
+MG_FLAG_ZERO_GUESS, MG_FLAG_TIMING, MG_FLAG_FCG = 1, 2, 4
 MG_HIST_MAX = 256
 MG_MAX_LEVELS = 16
-MG_K_SWEEP, MG_K_RESTRICT, MG_K_PROLONG, MG_K_OUTER, MG_K_NORM, MG_K_COUNT = 0, 1, 2, 3, 4, 5
+MG_K_SWEEP, MG_K_RESTRICT, MG_K_PROLONG, MG_K_OUTER, MG_K_NORM, MG_K_SWEEP2, MG_K_COUNT = 0, 1, 2, 3, 4, 5, 6
 
 STATUS_NAMES = {
     MG_OK: "MG_OK", MG_EINVAL: "MG_EINVAL", MG_ENOMEM: "MG_ENOMEM", MG_EHIP: "MG_EHIP",
@@ -60,6 +60,8 @@ SIGNATURES = {
     "mg_last_error": (ctypes.c_char_p, [_CTX]),
     "mg_faces_from_vof": (_I, [_D, _D, _DIMS, _F, _F, _F, _D, _D, _D, ctypes.c_void_p]),
     "mg_divergence": (_I, [_D, _D, _D, _DIMS, _F, _F, _D, ctypes.c_void_p]),
+    "mg_vof_grad": (_I, [_D, _D, _DIMS, _F, _F, _F, _D, _D, _D, _D, _D, ctypes.c_void_p]),
+    "mg_velocity_correct": (_I, [_D, _D, _D, _D, _DIMS, _F, _F, _D, _D, _D, ctypes.c_void_p]),
     "mg_plan_levels": (_I, [_DIMS, _I]),
     "mg_level_info": (_I, [_CTX, _I, _DIMS, ctypes.POINTER(ctypes.c_double)]),
     "mg_level_faces": (_I, [_CTX, _I, _D, _D, _D]),

@@ -9,11 +9,15 @@ Backward, for an upstream gradient w = dLoss/dp:
                   (one fused face-gradient kernel), 0 on walls.
 p is recomputed in the backward pass from the saved (rhs, beta) unless
 save_p=True; no V-cycle state is stored.
+
+faces_from_vof chains the gradient one step further, to the VOF fractions the
+face coefficients are built from (mixture density, then harmonic-mean faces).
 """
 from __future__ import annotations
 
 import torch
 
+from . import solver as _S
 from .solver import Solver
 
 
@@ -59,3 +63,27 @@ def poisson_solve(rhs, beta_x, beta_y, beta_z, h, tol: float = 1e-10, precision:
                   save_p: bool = False):
     """Differentiable zero-mean solve of div(beta grad p) = rhs - mean(rhs)."""
     return PoissonSolve.apply(rhs, beta_x, beta_y, beta_z, h, tol, precision, save_p)
+
+
+class FacesFromVof(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, f_drop, f_film, rho_drop, rho_film, rho_gas):
+        f_drop, f_film = f_drop.contiguous(), f_film.contiguous()
+        ctx.rho = (float(rho_drop), float(rho_film), float(rho_gas))
+        ctx.save_for_backward(f_drop, f_film)
+        return _S.faces_from_vof(f_drop, f_film, *ctx.rho)
+
+    @staticmethod
+    def backward(ctx, g_x, g_y, g_z):
+        f_drop, f_film = ctx.saved_tensors
+        shapes = _S.face_shapes(tuple(reversed(f_drop.shape)))
+        grads = [torch.zeros(s, dtype=torch.float64, device=f_drop.device) if g is None else g.contiguous()
+                 for g, s in zip((g_x, g_y, g_z), shapes)]
+        g_drop, g_film = _S.vof_grad(f_drop, f_film, *ctx.rho, *grads)
+        return (g_drop if ctx.needs_input_grad[0] else None, g_film if ctx.needs_input_grad[1] else None,
+                None, None, None)
+
+
+def faces_from_vof(f_drop, f_film, rho_drop: float, rho_film: float, rho_gas: float):
+    """Differentiable face coefficients (beta_x, beta_y, beta_z) from the VOF fractions."""
+    return FacesFromVof.apply(f_drop, f_film, rho_drop, rho_film, rho_gas)

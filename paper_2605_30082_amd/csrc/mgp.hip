@@ -14,6 +14,8 @@
 
 #include "mgp_kernels.hpp"
 #include "mgp_sweep.hpp"
+#include "mgp_sweep2.hpp"
+#include "mgp_krylov.hpp"
 #include "mgp_resid.hpp"
 #include "mgp_transfer.hpp"
 
@@ -52,6 +54,9 @@ struct mg_ctx {
     double* b0 = nullptr;        // projected rhs, finest
     double* ptmp = nullptr;      // ping-pong partner of the caller's p
     double* work = nullptr;      // scratch (coarse inverse build; verification copies)
+    double* fr = nullptr;        // flexible-CG residual, direction and L direction (MG_FLAG_FCG)
+    double* fd = nullptr;
+    double* fq = nullptr;
     double* partials = nullptr;  // kReduceBlocks
     double* scal = nullptr;      // device scalars
     double* host_scal = nullptr; // pinned host mirror
@@ -217,6 +222,45 @@ int sweep(mg_ctx* c, int l, const T* b, const T* in, T* out, int order, bool zer
     return MG_OK;
 }
 
+// Two sweeps of one order in one launch (FP32 grids that sweep2_ok accepts).
+int sweep_pair(mg_ctx* c, int l, const float* b, const float* in, float* out, int order, bool zero_in)
+{
+    Level& L = c->lev[l];
+    LevelBufs<float>& B = L.f32;
+    TimedLaunch tl(c, l, MG_K_SWEEP2, 2.0 * (double)L.n * sweep_bytes_per_cell<float>(), true);
+    const hipError_t e = launch_sweep2<float>(B.bx, B.by, B.bz, L.d, (float)(L.h * L.h), b, in, out, order,
+                                              zero_in, c->stream);
+    if (e != hipSuccess) {
+        set_err(c, "sweep launch failed: %s", hipGetErrorString(e));
+        return MG_EHIP;
+    }
+    return MG_OK;
+}
+
+// `count` sweeps of one order on level l from *x (zero_in: from 0) with *t as
+// the ping-pong partner; on return *x holds the result.  FP32 pairs of sweeps
+// run in the two-sweep kernel where the grid allows it.
+template <typename T>
+int smooth(mg_ctx* c, int l, const T* b, T** x, T** t, int order, int count, bool zero_in)
+{
+    int done = 0;
+    if constexpr (sizeof(T) == 4) {
+        if (sweep2_ok(c->lev[l].d, sizeof(T))) {
+            for (; count - done >= 2; done += 2) {
+                const int e = sweep_pair(c, l, b, *x, *t, order, zero_in && done == 0);
+                if (e != MG_OK) return e;
+                std::swap(*x, *t);
+            }
+        }
+    }
+    for (; done < count; ++done) {
+        const int e = sweep<T>(c, l, b, *x, *t, order, zero_in && done == 0);
+        if (e != MG_OK) return e;
+        std::swap(*x, *t);
+    }
+    return MG_OK;
+}
+
 template <typename T>
 int residual_restrict(mg_ctx* c, int l, const T* b, const T* x, T* bc)
 {
@@ -272,6 +316,14 @@ int fill(mg_ctx* c, T* x, long n, T v)
     return MG_OK;
 }
 
+template <typename S, typename D>
+int convert(mg_ctx* c, const S* x, long n, D* y)
+{
+    k_convert<S, D><<<grid_for(n), kBlock, 0, c->stream>>>(x, n, y);
+    CHECK_LAUNCH(c);
+    return MG_OK;
+}
+
 #define TRY(...)                    \
     do {                            \
         int s_ = (__VA_ARGS__);     \
@@ -288,10 +340,7 @@ int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init)
     if (l == c->nlev - 1) return coarse_apply<T>(c, b, *x);
     const int pre = c->opts.pre, post = c->opts.post;
     if (zero_init && pre == 0) TRY(fill<T>(c, *x, L.n, (T)0));
-    for (int s = 0; s < pre; ++s) {
-        TRY(sweep<T>(c, l, b, *x, *t, 0, zero_init && s == 0));
-        std::swap(*x, *t);
-    }
+    TRY(smooth<T>(c, l, b, x, t, 0, pre, zero_init));
     Level& C = c->lev[l + 1];
     LevelBufs<T>& CB = bufs<T>(C);
     TRY(residual_restrict<T>(c, l, b, *x, CB.b));
@@ -299,10 +348,7 @@ int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init)
     T* ct = CB.t;
     TRY(vcycle<T>(c, l + 1, &cx, &ct, CB.b, true));
     TRY(prolong_correct<T>(c, l, cx, *x));
-    for (int s = 0; s < post; ++s) {
-        TRY(sweep<T>(c, l, b, *x, *t, 1, false));
-        std::swap(*x, *t);
-    }
+    TRY(smooth<T>(c, l, b, x, t, 1, post, false));
     return MG_OK;
 }
 
@@ -345,6 +391,89 @@ int outer_update(mg_ctx* c, const double* p_in, const float* e, double* p_out, f
                                                             c->b0, p_in, e, e ? 0 : 1, p_out, r32, c->partials);
     CHECK_LAUNCH(c);
     return reduce_to(c, kReduceBlocks, slot);
+}
+
+// ---------------------------------------------------------------------------
+// flexible CG preconditioned by one V-cycle (MG_FLAG_FCG)
+// ---------------------------------------------------------------------------
+
+constexpr int kSlotRR = 2, kSlotZQ = 6, kSlotDQ = 7, kSlotDR = 8;
+
+template <typename TZ>
+int fcg_step(mg_ctx* c, const TZ* z, double* x, float* r32, bool first, double dq_prev)
+{
+    Level& F = c->lev[0];
+    const long n = F.n;
+    if (!first) {
+        k_fcg_dot<TZ><<<kReduceBlocks, kBlock, 0, c->stream>>>(z, c->fq, n, c->partials);
+        CHECK_LAUNCH(c);
+        TRY(reduce_to(c, kReduceBlocks, kSlotZQ));
+    }
+    k_fcg_direction<TZ><<<grid_for(n), kBlock, 0, c->stream>>>(z, c->fd, n, c->scal, kSlotZQ, dq_prev,
+                                                                first ? 1 : 0);
+    CHECK_LAUNCH(c);
+    k_fcg_apply<<<kReduceBlocks, kBlock, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, F.d, 1.0 / (F.h * F.h),
+                                                         c->fd, c->fr, c->fq, c->partials);
+    CHECK_LAUNCH(c);
+    TRY(reduce_to(c, kReduceBlocks, kSlotDQ));
+    k_reduce_final<<<1, kBlock, 0, c->stream>>>(c->partials + kReduceBlocks, kReduceBlocks, c->scal, kSlotDR);
+    CHECK_LAUNCH(c);
+    k_fcg_update<<<kReduceBlocks, kBlock, 0, c->stream>>>(x, c->fr, c->fd, c->fq, n, c->scal, kSlotDR, kSlotDQ,
+                                                          r32, c->partials);
+    CHECK_LAUNCH(c);
+    return reduce_to(c, kReduceBlocks, kSlotRR);
+}
+
+// Iterates on x (the caller's p) until ||r|| <= tol ||b0||; r is the updated
+// residual.  Same statuses and divergence guard as the V-cycle loops.
+int fcg_loop(mg_ctx* c, double* x, double bnorm, double tol, bool zero_guess, mg_stats* st, int* cycles_out,
+             double* rr_out, int* status_out)
+{
+    Level& F = c->lev[0];
+    const long n = F.n;
+    float* r32 = c->mixed ? F.f32.b : nullptr;
+    double rr = 1.0;
+    if (zero_guess) {
+        TRY(fill<double>(c, x, n, 0.0));
+        HIP_TRY(c, hipMemcpyAsync(c->fr, c->b0, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        TRY(residual_norm_launch(c, c->b0, x, c->fr, kSlotRR));
+        TRY(fetch_scalars(c, kSlotRR + 1));
+        rr = std::sqrt(c->host_scal[kSlotRR]) / bnorm;
+    }
+    if (r32) TRY(convert<double, float>(c, c->fr, n, r32));
+    if (st) st->hist[0] = rr;
+    int status = MG_ENOCONV, it = 0;
+    if (!std::isfinite(rr)) status = MG_ENONFINITE;
+    else if (rr <= tol) status = MG_OK;
+    double best = rr, dq_prev = 0.0;
+    while (status == MG_ENOCONV && it < c->opts.max_cycles) {
+        const bool first = it == 0;
+        if (c->mixed) {
+            float* zx = F.f32.x;
+            float* zt = F.f32.t;
+            TRY(vcycle<float>(c, 0, &zx, &zt, r32, true));
+            TRY(fcg_step<float>(c, zx, x, r32, first, dq_prev));
+        } else {
+            double* zx = F.f64.x;
+            double* zt = F.f64.t;
+            TRY(vcycle<double>(c, 0, &zx, &zt, c->fr, true));
+            TRY(fcg_step<double>(c, zx, x, nullptr, first, dq_prev));
+        }
+        TRY(fetch_scalars(c, kSlotDR + 1));
+        dq_prev = c->host_scal[kSlotDQ];
+        ++it;
+        rr = std::sqrt(c->host_scal[kSlotRR]) / bnorm;
+        if (st && it < MG_HIST_MAX) st->hist[it] = rr;
+        if (!std::isfinite(rr)) { status = MG_ENONFINITE; break; }
+        if (rr <= tol) { status = MG_OK; break; }
+        best = std::min(best, rr);
+        if (rr > 1e3 * best) break;
+    }
+    *cycles_out = it;
+    *rr_out = rr;
+    *status_out = status;
+    return MG_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -424,7 +553,9 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
     double* cur = p;        // buffer holding the current iterate
     double* other = c->ptmp;
 
-    if (!c->mixed) {
+    if (c->opts.flags & MG_FLAG_FCG) {
+        TRY(fcg_loop(c, cur, bnorm, tol, zero_guess, st, &cycles, &rr, &status));
+    } else if (!c->mixed) {
         if (zero_guess) {
             rr = 1.0;
         } else {
@@ -548,6 +679,11 @@ void carve(mg_ctx* c, Arena& a)
     c->work = a.take<double>(std::max<long>(m * 2 * m, n0));
     c->partials = a.take<double>(kMaxPartials);
     c->scal = a.take<double>(16);
+    if (c->opts.flags & MG_FLAG_FCG) {
+        c->fr = a.take<double>(n0);
+        c->fd = a.take<double>(n0);
+        c->fq = a.take<double>(n0);
+    }
     for (int l = 0; l < c->nlev; ++l) {
         Level& L = c->lev[l];
         L.f64.bx = a.take<double>(n_fx(L.d));
@@ -626,14 +762,6 @@ int level_ok(mg_ctx* c, int level, int precision)
     return MG_OK;
 }
 
-template <typename S, typename D>
-int convert(mg_ctx* c, const S* x, long n, D* y)
-{
-    k_convert<S, D><<<grid_for(n), kBlock, 0, c->stream>>>(x, n, y);
-    CHECK_LAUNCH(c);
-    return MG_OK;
-}
-
 }  // namespace
 
 // ===========================================================================
@@ -680,7 +808,7 @@ int mg_setup(mg_ctx** out, const double* beta_x, const double* beta_y, const dou
     if (o.pre < 0 || o.pre > 8 || o.post < 0 || o.post > 8 || o.pre + o.post == 0 || o.max_cycles < 1 ||
         o.max_cycles >= MG_HIST_MAX || o.coarse_max < 1 || o.coarse_max > 4 ||
         (o.precision != MG_PREC_FP64 && o.precision != MG_PREC_MIXED) ||
-        (o.flags & ~(MG_FLAG_ZERO_GUESS | MG_FLAG_TIMING))) {
+        (o.flags & ~(MG_FLAG_ZERO_GUESS | MG_FLAG_TIMING | MG_FLAG_FCG))) {
         set_err(c, "invalid options");
         return fail(MG_EINVAL);
     }
@@ -839,6 +967,33 @@ int mg_divergence(const double* u, const double* v, const double* w, const int d
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 
+int mg_vof_grad(const double* f_drop, const double* f_film, const int dims[3], double rho_drop, double rho_film,
+                double rho_gas, const double* g_x, const double* g_y, const double* g_z, double* g_drop,
+                double* g_film, void* hip_stream)
+{
+    if (!f_drop || !f_film || !dims || !g_x || !g_y || !g_z || !g_drop || !g_film) return MG_EINVAL;
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || !(rho_drop > 0) || !(rho_film > 0) || !(rho_gas > 0))
+        return MG_EINVAL;
+    const Dims d{dims[0], dims[1], dims[2]};
+    const long n = (long)d.nx * d.ny * d.nz;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    k_vof_grad<<<grid_for(n), kBlock, 0, s>>>(f_drop, f_film, d, rho_drop, rho_film, rho_gas, g_x, g_y, g_z, g_drop,
+                                             g_film);
+    return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
+}
+
+int mg_velocity_correct(const double* beta_x, const double* beta_y, const double* beta_z, const double* p,
+                        const int dims[3], double h, double dt, double* u, double* v, double* w, void* hip_stream)
+{
+    if (!beta_x || !beta_y || !beta_z || !p || !dims || !u || !v || !w) return MG_EINVAL;
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || !(h > 0) || !(dt > 0)) return MG_EINVAL;
+    const Dims d{dims[0], dims[1], dims[2]};
+    const long nf = (long)d.nz * d.ny * (d.nx + 1) + (long)d.nz * (d.ny + 1) * d.nx + (long)(d.nz + 1) * d.ny * d.nx;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    k_velocity_correct<<<grid_for(nf), kBlock, 0, s>>>(beta_x, beta_y, beta_z, p, d, h, dt, u, v, w);
+    return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
+}
+
 int mg_level_info(const mg_ctx* cc, int level, int dims[3], double* h)
 {
     mg_ctx* c = as_ctx(cc);
@@ -880,10 +1035,7 @@ int mg_smooth(mg_ctx* c, int level, int precision, const double* b, double* p, i
         double* x = level == 0 ? c->work : L.f64.x;
         double* t = level == 0 ? c->ptmp : L.f64.t;
         HIP_TRY(c, hipMemcpyAsync(x, p, sizeof(double) * L.n, hipMemcpyDeviceToDevice, c->stream));
-        for (int s = 0; s < nsweeps; ++s) {
-            TRY(sweep<double>(c, level, b, x, t, order, false));
-            std::swap(x, t);
-        }
+        TRY(smooth<double>(c, level, b, &x, &t, order, nsweeps, false));
         HIP_TRY(c, hipMemcpyAsync(p, x, sizeof(double) * L.n, hipMemcpyDeviceToDevice, c->stream));
     } else {
         float* x = L.f32.x;
@@ -891,10 +1043,7 @@ int mg_smooth(mg_ctx* c, int level, int precision, const double* b, double* p, i
         float* bb = L.f32.b;
         TRY(convert<double, float>(c, b, L.n, bb));
         TRY(convert<double, float>(c, p, L.n, x));
-        for (int s = 0; s < nsweeps; ++s) {
-            TRY(sweep<float>(c, level, bb, x, t, order, false));
-            std::swap(x, t);
-        }
+        TRY(smooth<float>(c, level, bb, &x, &t, order, nsweeps, false));
         TRY(convert<float, double>(c, x, L.n, p));
     }
     return MG_OK;

@@ -644,4 +644,75 @@ __global__ void k_divergence(const double* __restrict__ u, const double* __restr
     }
 }
 
+// dL/df_drop and dL/df_film per cell from dL/dbeta on the faces (public
+// layouts), gathered over the cell's interior faces:
+//   dL/drho_c = sum_f dL/dbeta_f * (-2 / (rho_c + rho_nb)^2)
+//   dL/df     = dL/drho_c * (rho_phase - rho_gas), rho_gas dropped where the
+//               gas fraction 1 - f_drop - f_film is clamped (negative).
+__global__ void k_vof_grad(const double* __restrict__ fd, const double* __restrict__ ff, Dims d, double rd,
+                           double rf, double rg, const double* __restrict__ gx, const double* __restrict__ gy,
+                           const double* __restrict__ gz, double* __restrict__ g_drop, double* __restrict__ g_film)
+{
+#pragma clang fp contract(off)
+    const long n = (long)d.nx * d.ny * d.nz;
+    const long sz = (long)d.nx * d.ny;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
+        int i, j, k;
+        cell_of(c, d, i, j, k);
+        const double rc = cell_density(fd[c], ff[c], rd, rf, rg);
+        const long fx = ((long)k * d.ny + j) * (d.nx + 1) + i;
+        const long fy = ((long)k * (d.ny + 1) + j) * d.nx + i;
+        double acc = 0.0;
+        auto face = [&](long nb, double g) {
+            const double s = rc + cell_density(fd[nb], ff[nb], rd, rf, rg);
+            acc += g * (-2.0 / (s * s));
+        };
+        if (i > 0) face(c - 1, gx[fx]);
+        if (i < d.nx - 1) face(c + 1, gx[fx + 1]);
+        if (j > 0) face(c - d.nx, gy[fy]);
+        if (j < d.ny - 1) face(c + d.nx, gy[fy + d.nx]);
+        if (k > 0) face(c - sz, gz[c]);
+        if (k < d.nz - 1) face(c + sz, gz[c + sz]);
+        const double gas = (1.0 - fd[c] - ff[c] < 0.0) ? 0.0 : rg;
+        g_drop[c] = acc * (rd - gas);
+        g_film[c] = acc * (rf - gas);
+    }
+}
+
+// u_f -= dt * beta_f * (p_R - p_L) / h on interior faces of the public face
+// layouts (evaluated left to right, no contraction); one thread per face.
+__global__ void k_velocity_correct(const double* __restrict__ bx, const double* __restrict__ by,
+                                   const double* __restrict__ bz, const double* __restrict__ p, Dims d, double h,
+                                   double dt, double* __restrict__ u, double* __restrict__ v, double* __restrict__ w)
+{
+#pragma clang fp contract(off)
+    const long nfx = (long)d.nz * d.ny * (d.nx + 1);
+    const long nfy = (long)d.nz * (d.ny + 1) * d.nx;
+    const long nfz = (long)(d.nz + 1) * d.ny * d.nx;
+    const long sz = (long)d.nx * d.ny;
+    for (long f = (long)blockIdx.x * kBlock + threadIdx.x; f < nfx + nfy + nfz; f += (long)gridDim.x * kBlock) {
+        if (f < nfx) {
+            const int i = (int)(f % (d.nx + 1));
+            const long row = f / (d.nx + 1);
+            if (i == 0 || i == d.nx) continue;
+            const long c = row * d.nx + i;
+            u[f] = u[f] - dt * bx[f] * (p[c] - p[c - 1]) / h;
+        } else if (f < nfx + nfy) {
+            const long g = f - nfx;
+            const int i = (int)(g % d.nx);
+            const long r = g / d.nx;
+            const int j = (int)(r % (d.ny + 1));
+            const long k = r / (d.ny + 1);
+            if (j == 0 || j == d.ny) continue;
+            const long c = (k * d.ny + j) * d.nx + i;
+            v[g] = v[g] - dt * by[g] * (p[c] - p[c - d.nx]) / h;
+        } else {
+            const long g = f - nfx - nfy;
+            const long k = g / sz;
+            if (k == 0 || k == d.nz) continue;
+            w[g] = w[g] - dt * bz[g] * (p[g] - p[g - sz]) / h;
+        }
+    }
+}
+
 }  // namespace mgp

@@ -1,0 +1,260 @@
+// Two red-black Gauss-Seidel sweeps in one pass over memory (temporal blocking).
+//
+// Two full sweeps with colour order (A, B) are four half-sweeps A1, B1, A2, B2:
+//   A1: A-cells from `in`;  B1: B-cells from A1;  A2: A-cells from B1;
+//   B2: B-cells from A2.    out = (A2 on A-cells, B2 on B-cells).
+// A half-sweep of a cell reads only its six face neighbours, which have the
+// other colour, so a stage on plane z needs the previous stage on planes
+// z-1, z, z+1.  A block that owns a 64 x TY tile of (x, y) marches a chunk of
+// z with the stages staggered in z, per step s (three LDS barriers):
+//   phase 1: A1 on plane s   (tile + 3-cell ring)   and   B2 on plane s-4 (tile)
+//   phase 2: B1 on plane s-1 (tile + 2-cell ring)
+//   phase 3: A2 on plane s-2 (tile + 1-cell ring)
+// A1(s) and B2(s-4) touch disjoint planes, so they share a phase.  The rings
+// shrink by one cell per stage, so every value a tile cell needs is computed
+// inside the block: no block waits for another.  Every plane holds the newest
+// value of each of its cells in one LDS slot (8 slots cover planes s-5..s+1
+// plus the one being filled); stage order within a step guarantees that each
+// read sees the state it needs (e.g. B1(s-1) reads A-cells of s-2 before A2
+// overwrites them in the same step).
+//
+// Each thread owns one pair of x-adjacent cells of the tile + 4-cell ring
+// (36 pairs per row, TY + 8 rows): in every plane one cell of the pair is an
+// A-cell and the other a B-cell.  The coefficients of the pair's cells are
+// loaded once per plane, one step before first use, and kept in registers
+// for the five steps during which the four stages visit that plane.  The
+// previous iterate is read once and the result written once: the memory
+// traffic of one sweep for two sweeps of work, plus the ring re-reads.
+#pragma once
+
+#include "mgp_buffer.hpp"
+
+namespace mgp {
+
+template <int TY>
+struct Sweep2Geom {
+    static constexpr int TX = 64;              // tile width (cells)
+    static constexpr int EX = TX + 8;          // LDS plane: x0-4 .. x0+TX+3
+    static constexpr int EY = TY + 8;          //            y0-4 .. y0+TY+3
+    static constexpr int HX = EX / 2;          // pairs per row
+    static constexpr int NP = HX * EY;         // pairs per plane = working threads
+    static constexpr int NT = (NP + 63) / 64 * 64;
+    static constexpr int PLANE = EX * EY;
+    static constexpr int SLOTS = 8;
+    // LDS position of plane coordinates (ex, ey): each row keeps its even-x
+    // cells, then its odd-x cells (one colour of a row is contiguous).
+    __device__ static int idx(int ex, int ey) { return ey * EX + (ex & 1) * HX + (ex >> 1); }
+};
+
+// Launch contract: nx even and >= 64, every array below 2^31 bytes, grid =
+// ntx * nty * ceil(nz / zc) blocks of Sweep2Geom<TY>::NT threads.
+template <typename T, int TY>
+__global__ void __launch_bounds__(Sweep2Geom<TY>::NT)
+k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
+               const T* __restrict__ bb, const T* __restrict__ in, T* __restrict__ out, Dims d, T h2, int c0,
+               int zero_in, int zc, int ntx, int nty)
+{
+    using G = Sweep2Geom<TY>;
+    using T2 = typename Vec2<T>::type;
+    __shared__ T slot[G::SLOTS * G::PLANE];
+    const int nb = (int)gridDim.x, bid = (int)blockIdx.x;
+    const int q8 = nb / 8, r8 = nb % 8, xcd = bid % 8;
+    const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / 8;
+    const int tx = logical % ntx, ty = (logical / ntx) % nty, tz = logical / (ntx * nty);
+    const int x0 = tx * G::TX, y0 = ty * TY, z0 = tz * zc;
+    const int z1 = min(z0 + zc, d.nz);
+    const int t = (int)threadIdx.x;
+    const bool active = t < G::NP;
+    const int pxi = active ? t % G::HX : 0, pyi = active ? t / G::HX : 0;
+    const int gx0 = x0 - 4 + 2 * pxi, gy = y0 - 4 + pyi;
+    const bool inside = active && gx0 >= 0 && gx0 < d.nx && gy >= 0 && gy < d.ny;
+    // rows y0-4 and y0+TY+3 only supply neighbour values: no coefficients
+    const bool coef_row = inside && pyi >= 1 && pyi <= G::EY - 2;
+
+    const unsigned psz = (unsigned)((long)d.nx * d.ny * sizeof(T));
+    const unsigned pfx = (unsigned)((long)(d.nx + 2) * d.ny * sizeof(T));
+    const unsigned pfy = (unsigned)((long)d.nx * (d.ny + 1) * sizeof(T));
+    const unsigned rowb = (unsigned)(d.nx * sizeof(T));
+    const long ncell = (long)d.nx * d.ny * d.nz;
+    const auto r_b = make_rsrc(bb, (unsigned)(ncell * sizeof(T)));
+    const auto r_bx = make_rsrc(bx, (unsigned)(n_fx(d) * sizeof(T)));
+    const auto r_by = make_rsrc(by, (unsigned)(n_fy(d) * sizeof(T)));
+    const auto r_bz = make_rsrc(bz, (unsigned)(n_fz(d) * sizeof(T)));
+    const auto r_in = make_rsrc(in, (unsigned)(ncell * sizeof(T)));
+    const auto r_null = make_rsrc(in, 0u);
+    const unsigned oin = inside ? (unsigned)(gy * d.nx + gx0) * sizeof(T) : kOutside;
+    const unsigned oc = coef_row ? (unsigned)(gy * d.nx + gx0) * sizeof(T) : kOutside;
+    const unsigned ofx = coef_row ? (unsigned)(gy * (d.nx + 2) + gx0) * sizeof(T) : kOutside;
+    const int le = G::idx(2 * pxi, pyi), lo = G::idx(2 * pxi + 1, pyi);
+
+    auto cpl = [&](int z) { return (unsigned)min(max(z, 0), d.nz - 1); };
+    auto load_in = [&](int z) -> T2 {
+        const bool zv = !zero_in && z >= 0 && z < d.nz;
+        return bload2<T>(zv ? r_in : r_null, oin, cpl(z) * psz);
+    };
+    auto store_in = [&](int z, T2 v) {
+        if (active) {
+            T* s = slot + (z & (G::SLOTS - 1)) * G::PLANE;
+            s[le] = v.x;
+            s[lo] = v.y;
+        }
+    };
+    // coefficients of the pair in one plane; bz is the pair's lower z-face
+    struct Coef {
+        T2 b, bx, by, byu, bz;
+        T bxn;
+    };
+    auto load_coef = [&](int z, Coef& C) {
+        const unsigned zz = cpl(z);
+        C.b = bload2<T>(r_b, oc, zz * psz);
+        C.bx = bload2<T>(r_bx, ofx, zz * pfx);
+        C.bxn = bload1<T>(r_bx, ofx, zz * pfx + 2u * sizeof(T));
+        C.by = bload2<T>(r_by, oc, zz * pfy);
+        C.byu = bload2<T>(r_by, oc, zz * pfy + rowb);
+    };
+    auto load_bz = [&](int z) -> T2 { return bload2<T>(r_bz, oc, (unsigned)min(max(z, 0), d.nz) * psz); };
+
+    // Half-sweep of the colour-`col` cell of the pair on plane z, if that cell
+    // lies in the tile + r ring and in the domain; the value goes to `v`.
+    auto relax = [&](int z, int col, int r, const Coef& C, T2 bzu, bool& ok, int& li, T& v) {
+        const int odd = (gx0 + gy + z + col) & 1;
+        const int gx = gx0 + odd;
+        ok = inside && z >= 0 && z < d.nz && gx >= x0 - r && gx < x0 + G::TX + r && gx < d.nx && gy >= y0 - r &&
+             gy < y0 + TY + r;
+        const int ex = 2 * pxi + odd;
+        li = odd ? lo : le;
+        if (!ok) return;
+        const T* S = slot + (z & (G::SLOTS - 1)) * G::PLANE;
+        const T* Sm = slot + ((z - 1) & (G::SLOTS - 1)) * G::PLANE;
+        const T* Sp = slot + ((z + 1) & (G::SLOTS - 1)) * G::PLANE;
+        const T bxl = odd ? C.bx.y : C.bx.x;
+        const T bxh = odd ? C.bxn : C.bx.y;
+        const T byl = odd ? C.by.y : C.by.x;
+        const T byh = odd ? C.byu.y : C.byu.x;
+        const T bzl = odd ? C.bz.y : C.bz.x;
+        const T bzh = odd ? bzu.y : bzu.x;
+        const T b = odd ? C.b.y : C.b.x;
+        T dg = bxl, of = bxl * S[G::idx(ex - 1, pyi)];
+        dg += bxh; of += bxh * S[G::idx(ex + 1, pyi)];
+        dg += byl; of += byl * S[G::idx(ex, pyi - 1)];
+        dg += byh; of += byh * S[G::idx(ex, pyi + 1)];
+        dg += bzl; of += bzl * Sm[li];
+        dg += bzh; of += bzh * Sp[li];
+        v = quot(of - h2 * b, dg);
+    };
+
+    const int cA = c0, cB = 1 - c0;
+    const int sbeg = z0 - 3, send = z1 + 3;
+    store_in(sbeg - 1, load_in(sbeg - 1));
+    store_in(sbeg, load_in(sbeg));
+    T2 v = load_in(sbeg + 1);
+    Coef C0, C1, C2, C3, C4, Cn;
+    load_coef(sbeg, C0);
+    C0.bz = load_bz(sbeg);
+    T2 zn = load_bz(sbeg + 1);
+    C1 = C0;
+    C2 = C0;
+    C3 = C0;
+    C4 = C0;
+    const bool core = active && pxi >= 2 && pxi < 2 + G::HX - 4 && pyi >= 4 && pyi < 4 + TY && gy < d.ny &&
+                      gx0 < d.nx;
+
+    for (int s = sbeg; s <= send; ++s) {
+        store_in(s + 1, v);
+        v = load_in(s + 2);
+        load_coef(s + 1, Cn);
+        const T2 zn2 = load_bz(s + 2);
+        lds_barrier();
+        // phase 1: A1 on plane s, B2 on plane s-4 (written to memory)
+        if (s <= z1 + 2) {
+            bool ok;
+            int li;
+            T a;
+            relax(s, cA, 3, C0, zn, ok, li, a);
+            if (ok) slot[(s & (G::SLOTS - 1)) * G::PLANE + li] = a;
+        }
+        const int zb = s - 4;
+        if (zb >= z0 && core) {
+            bool ok;
+            int li;
+            T bv;
+            relax(zb, cB, 0, C4, C3.bz, ok, li, bv);
+            const T* S = slot + (zb & (G::SLOTS - 1)) * G::PLANE;
+            const bool bodd = li == lo;
+            const T av = S[bodd ? le : lo];
+            T2 o;
+            o.x = bodd ? av : bv;
+            o.y = bodd ? bv : av;
+            *reinterpret_cast<T2*>(out + (long)zb * d.nx * d.ny + (long)gy * d.nx + gx0) = o;
+        }
+        lds_barrier();
+        // phase 2: B1 on plane s-1
+        if (s - 1 >= z0 - 2 && s - 1 <= z1 + 1) {
+            bool ok;
+            int li;
+            T bv;
+            relax(s - 1, cB, 2, C1, C0.bz, ok, li, bv);
+            if (ok) slot[((s - 1) & (G::SLOTS - 1)) * G::PLANE + li] = bv;
+        }
+        lds_barrier();
+        // phase 3: A2 on plane s-2
+        if (s - 2 >= z0 - 1 && s - 2 <= z1) {
+            bool ok;
+            int li;
+            T a;
+            relax(s - 2, cA, 1, C2, C1.bz, ok, li, a);
+            if (ok) slot[((s - 2) & (G::SLOTS - 1)) * G::PLANE + li] = a;
+        }
+        C4 = C3;
+        C3 = C2;
+        C2 = C1;
+        C1 = C0;
+        C0 = Cn;
+        C0.bz = zn;
+        zn = zn2;
+    }
+}
+
+// Blocks of the two-sweep kernel: z is cut into chunks of at least 32 planes
+// (each chunk re-walks 7 planes of stage lag) so that the grid holds about
+// 1024 blocks.
+struct Sweep2Launch {
+    int ntx, nty, zc, blocks;
+};
+
+template <int TY>
+inline Sweep2Launch sweep2_geom(const Dims& d)
+{
+    Sweep2Launch g;
+    g.ntx = (d.nx + 63) / 64;
+    g.nty = (d.ny + TY - 1) / TY;
+    const int tiles = g.ntx * g.nty;
+    int nzc = (1024 + tiles - 1) / tiles;
+    int zc = (d.nz + nzc - 1) / nzc;
+    if (zc < 32) zc = 32;
+    if (zc > d.nz) zc = d.nz;
+    g.zc = zc;
+    g.blocks = tiles * ((d.nz + zc - 1) / zc);
+    return g;
+}
+
+// Grids the two-sweep kernel serves: at least 64 cells wide (even) and 16
+// rows, arrays below 2^31 bytes.
+inline bool sweep2_ok(const Dims& d, size_t elem)
+{
+    const long big = n_fx(d) > n_fz(d) ? n_fx(d) : n_fz(d);
+    return elem == 4 && d.nx >= 64 && (d.nx % 2) == 0 && d.ny >= 16 && big * (long)elem < (1L << 31);
+}
+
+template <typename T>
+hipError_t launch_sweep2(const T* bx, const T* by, const T* bz, Dims d, T h2, const T* b, const T* in, T* out,
+                         int order, bool zero_in, hipStream_t s)
+{
+    constexpr int TY = 16;
+    const Sweep2Launch g = sweep2_geom<TY>(d);
+    k_sweep2_fused<T, TY><<<g.blocks, Sweep2Geom<TY>::NT, 0, s>>>(bx, by, bz, b, in, out, d, h2, order == 0 ? 0 : 1,
+                                                                   zero_in ? 1 : 0, g.zc, g.ntx, g.nty);
+    return hipGetLastError();
+}
+
+}  // namespace mgp

@@ -80,7 +80,7 @@ class Solver:
     def __init__(self, beta_x: torch.Tensor, beta_y: torch.Tensor, beta_z: torch.Tensor, h: float,
                  bc: str = "neumann", precision: str = "fp64", pre: int = 2, post: int = 2,
                  max_cycles: int = 100, coarse_max: int = 4, zero_guess: bool = False,
-                 timing: bool = False, stream: Optional[torch.cuda.Stream] = None):
+                 timing: bool = False, stream: Optional[torch.cuda.Stream] = None, method: str = "vcycle"):
         self._lib = L.load()
         self._ctx = ctypes.c_void_p(None)
         if bc != "neumann":
@@ -93,7 +93,11 @@ class Solver:
         prec = {"fp64": L.MG_PREC_FP64, "mixed": L.MG_PREC_MIXED}.get(precision)
         if prec is None:
             raise MgError(L.MG_EINVAL, f"precision must be 'fp64' or 'mixed' (got {precision!r})")
-        flags = (L.MG_FLAG_ZERO_GUESS if zero_guess else 0) | (L.MG_FLAG_TIMING if timing else 0)
+        if method not in ("vcycle", "fcg"):
+            raise MgError(L.MG_EINVAL, f"method must be 'vcycle' or 'fcg' (got {method!r})")
+        self.method = method
+        flags = ((L.MG_FLAG_ZERO_GUESS if zero_guess else 0) | (L.MG_FLAG_TIMING if timing else 0)
+                 | (L.MG_FLAG_FCG if method == "fcg" else 0))
         self.opts = L.MgOpts(pre, post, max_cycles, coarse_max, prec, flags)
         self._stream = stream
         self._sh = _stream_handle(stream)
@@ -269,3 +273,34 @@ def divergence(u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, h: float, dt: 
                                 L.dims_arg(dims), float(h), float(dt), _ptr(b, "b"), _stream_handle(stream))
     L.check(st)
     return b
+
+
+def velocity_correct(bx: torch.Tensor, by: torch.Tensor, bz: torch.Tensor, p: torch.Tensor,
+                     u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, h: float, dt: float = 1.0,
+                     stream: Optional[torch.cuda.Stream] = None) -> None:
+    """In place on the GPU: u_f -= dt beta_f (p_R - p_L)/h on interior faces."""
+    nz, ny, nx = p.shape
+    dims = (nx, ny, nz)
+    shapes = face_shapes(dims)
+    st = L.load().mg_velocity_correct(_ptr(bx, "beta_x", shapes[0]), _ptr(by, "beta_y", shapes[1]),
+                                      _ptr(bz, "beta_z", shapes[2]), _ptr(p, "p", (nz, ny, nx)),
+                                      L.dims_arg(dims), float(h), float(dt), _ptr(u, "u", shapes[0]),
+                                      _ptr(v, "v", shapes[1]), _ptr(w, "w", shapes[2]), _stream_handle(stream))
+    L.check(st)
+
+
+def vof_grad(f_drop: torch.Tensor, f_film: torch.Tensor, rho_drop: float, rho_film: float, rho_gas: float,
+             g_x: torch.Tensor, g_y: torch.Tensor, g_z: torch.Tensor,
+             stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """(dL/df_drop, dL/df_film) from dL/dbeta on the faces, on the GPU."""
+    nz, ny, nx = f_drop.shape
+    dims = (nx, ny, nz)
+    shapes = face_shapes(dims)
+    gd = torch.empty_like(f_drop)
+    gf = torch.empty_like(f_drop)
+    st = L.load().mg_vof_grad(_ptr(f_drop, "f_drop", (nz, ny, nx)), _ptr(f_film, "f_film", (nz, ny, nx)),
+                              L.dims_arg(dims), float(rho_drop), float(rho_film), float(rho_gas),
+                              _ptr(g_x, "g_x", shapes[0]), _ptr(g_y, "g_y", shapes[1]), _ptr(g_z, "g_z", shapes[2]),
+                              _ptr(gd, "g_drop"), _ptr(gf, "g_film"), _stream_handle(stream))
+    L.check(st)
+    return gd, gf

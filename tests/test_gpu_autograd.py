@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import refs
-from gpu_util import N, T, gpu_inputs, note, oracle_inputs, rel_l2
+from gpu_util import N, T, gpu_inputs, max_rel, note, oracle_inputs, rel_l2
 from paper_2605_30082_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -139,3 +139,52 @@ def test_save_p_and_partial_requires_grad():
     rhs2 = leaf(gd + 3.0)
     p2 = poisson_solve(rhs2, gb[0], gb[1], gb[2], wl.h, tol=1e-12)
     assert rel_l2(N(p2), N(p)) < 1e-10
+
+
+def test_vof_grad_kernel_matches_oracle():
+    dims = (37, 22, 13)
+    nx, ny, nz = dims
+    g = np.random.default_rng(41)
+    fd = g.uniform(0, 0.8, (nz, ny, nx))
+    ff = g.uniform(0, 0.8, (nz, ny, nx))    # fd + ff > 1 in many cells: clamped gas
+    gb = [g.standard_normal(s) for s in S.face_shapes(dims)]
+    got = S.vof_grad(T(fd), T(ff), 1000.0, 960.0, 1.2, *[T(a) for a in gb])
+    ref = oracle.vof_grad(fd, ff, 1000.0, 960.0, 1.2, gb)
+    for a, r in zip(got, ref):
+        assert max_rel(N(a), r) < 1e-13
+
+
+def test_gradient_reaches_vof_fractions():
+    from paper_2605_30082_amd.autograd import faces_from_vof
+    wl = W.drop_film_workload(16)
+    w = W.loss_weights(wl.dims)
+    rd, rf, rg = wl.rho_drop, wl.rho_film, wl.rho_gas
+    fd, ff = leaf(T(wl.f_drop)), leaf(T(wl.f_film))
+    rhs = S.divergence(T(wl.u), T(wl.v), T(wl.w), wl.h, wl.dt)
+    bx, by, bz = faces_from_vof(fd, ff, rd, rf, rg)
+    p = poisson_solve(rhs, bx, by, bz, wl.h, tol=1e-12)
+    (T(w) * p).sum().backward()
+    gd, gf = N(fd.grad), N(ff.grad)
+    # the oracle's chain: adjoint solve, face gradient, then density and faces
+    ob, od = oracle_inputs(wl)
+    _, _, gbeta = oracle.gradients(ob, od, w, wl.h, tol=1e-13)
+    rd_ref, rf_ref = oracle.vof_grad(wl.f_drop, wl.f_film, rd, rf, rg, gbeta)
+    assert rel_l2(gd, rd_ref) < 1e-8 and rel_l2(gf, rf_ref) < 1e-8
+    # finite differences of the oracle's composition at interface cells
+    p0 = oracle.solve(ob, od, wl.h, tol=1e-13).p
+
+    def loss(a, b):
+        beta = oracle.faces_from_vof(a, b, rd, rf, rg)
+        return float(np.sum(w * oracle.solve(beta, od, wl.h, tol=1e-13, p0=p0).p))
+
+    gmax = np.abs(gd).max()
+    cand = np.argwhere((wl.f_drop > 0.05) & (wl.f_drop < 0.95) & (wl.f_drop + wl.f_film < 0.99))
+    pick = np.random.default_rng(42).choice(len(cand), 4, replace=False)
+    eps = 1e-4
+    for t in pick:
+        idx = tuple(cand[t])
+        a, b = wl.f_drop.copy(), wl.f_drop.copy()
+        a[idx] += eps
+        b[idx] -= eps
+        fdiff = (loss(a, wl.f_film) - loss(b, wl.f_film)) / (2 * eps)
+        assert abs(fdiff - gd[idx]) <= 1e-4 * abs(gd[idx]) + 1e-6 * gmax, (idx, fdiff, gd[idx])

@@ -81,6 +81,11 @@ def test_single_kernels_512(big, precision):
         for c in ((0, 1) if order == 0 else (1, 0)):
             ref = oracle.rbgs_half(ob, od, ref, wl.h, c)
         assert max_rel(got, ref) < tol, (order, max_rel(got, ref))
+        # two sweeps: one launch of the two-sweep kernel in FP32
+        got = N(s.smooth(gd, T(p), level=0, sweeps=2, order=order, precision=precision))
+        for c in ((0, 1) if order == 0 else (1, 0)):
+            ref = oracle.rbgs_half(ob, od, ref, wl.h, c)
+        assert max_rel(got, ref) < tol, (order, "2 sweeps", max_rel(got, ref))
     got = N(s.residual_restrict(gd, T(p), level=0, precision=precision))
     ref = oracle.restrict(oracle.residual(ob, od, p, wl.h))
     assert max_rel(got, ref) < tol * 10
@@ -163,3 +168,21 @@ def test_spheroid_film_256_mixed():
         assert err < 1e-9
         assert true_rr(ob, od, out[precision], wl.h) <= 1.000001e-10
         s.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_fcg_512(big, precision):
+    wl, gb, gd, ob, od = big
+    meta, idx, val = read_golden()
+    s = S.Solver(*gb, wl.h, precision=precision, zero_guess=True, method="fcg")
+    p, st = s.solve(gd, 1e-10)
+    s.close()
+    pg = N(p)
+    rr = true_rr(ob, od, pg, wl.h)
+    d = pg.ravel()[idx] - val["tol12"]
+    rms = meta["tol12_norm2"] / np.sqrt(512 ** 3)
+    sampled = float(np.sqrt(np.mean(d ** 2)) / rms)
+    note(f"fcg 512^3 {precision}: iterations {st.cycles} rr {st.rel_res:.3e} (oracle-recomputed {rr:.3e}), "
+         f"sampled rel vs converged oracle {sampled:.3e}")
+    assert st.rel_res <= 1e-10 and rr <= 1.01e-10
+    assert sampled < 1e-9

@@ -66,6 +66,30 @@ def test_faces_and_divergence_bitexact(make, n):
     np.testing.assert_array_equal(N(gd), od)
 
 
+@pytest.mark.parametrize("make,n", [(W.drop_film_workload, 48), (W.sphere_workload, 32)])
+def test_velocity_correct_bitexact_and_projects(make, n):
+    note(f"velocity correction {make.__name__} n={n}")
+    wl = make(n)
+    gb, gd = gpu_inputs(wl)
+    ob, od = oracle_inputs(wl)
+    s = S.Solver(*gb, wl.h, zero_guess=True)
+    p, st = s.solve(gd, 1e-12)
+    pg = N(p)
+    s.close()
+    dt = 0.37
+    gu, gv, gw = T(wl.u), T(wl.v), T(wl.w)
+    S.velocity_correct(*gb, p, gu, gv, gw, wl.h, dt)
+    ou, ov, ow = oracle.velocity_correct(ob, pg, wl.u, wl.v, wl.w, wl.h, dt)
+    for a, r in zip((gu, gv, gw), (ou, ov, ow)):
+        np.testing.assert_array_equal(N(a), r)
+    # projection: div_h u_new = div_h u - dt L p, and L p = (b - mean b) - r with r
+    # the solve's residual (b = div_h u / wl.dt)
+    div_new = N(S.divergence(gu, gv, gw, wl.h, 1.0))
+    r = od - od.mean() - oracle.apply(ob, pg, wl.h)
+    expect = wl.dt * od - dt * (od - od.mean()) + dt * r
+    assert np.abs(div_new - expect).max() <= 1e-9 * np.abs(od).max()
+
+
 def test_faces_from_vof_with_overfilled_cells():
     g = np.random.default_rng(5)
     fd = g.uniform(0, 1, (6, 5, 7))
@@ -129,6 +153,30 @@ def test_smooth(dims, precision):
                     for c in colours:
                         ref = oracle.rbgs_half(lb, b, ref, hl, c)
                 assert max_rel(got, ref) < tol, (lev, order, sweeps, max_rel(got, ref))
+    s.close()
+
+
+# FP32 sweeps on grids at least 64 x 16 wide go in pairs through the two-sweep
+# kernel: (64, 32, 48) has a ragged last z-chunk, (96, 64, 32) a ragged last x-tile;
+# 3 sweeps = one pair + one single sweep.
+@pytest.mark.parametrize("dims", [(64, 32, 48), (96, 64, 32), (128, 64, 64)])
+def test_smooth_fp32_sweep_pairs(dims):
+    note(f"fp32 sweep pairs dims={dims}")
+    beta = random_beta(dims, 13)
+    h = 1.0 / dims[0]
+    s = make_solver(beta, h, precision="mixed")
+    lb = [N(a) for a in s.level_faces(0)]
+    b = random_cells(dims, 14)
+    p = random_cells(dims, 15)
+    for order in (0, 1):
+        for sweeps in (2, 3, 4):
+            got = N(s.smooth(T(b), T(p), level=0, sweeps=sweeps, order=order, precision="mixed"))
+            ref = p.copy()
+            colours = (0, 1) if order == 0 else (1, 0)
+            for _ in range(sweeps):
+                for c in colours:
+                    ref = oracle.rbgs_half(lb, b, ref, h, c)
+            assert max_rel(got, ref) < 2e-6, (order, sweeps, max_rel(got, ref))
     s.close()
 
 

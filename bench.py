@@ -47,19 +47,20 @@ KERNEL_SYMBOLS = {
     ("residual_norm", "fp64"): "mgp::k_resid<double, 0>",
 }
 
-# HBM bytes per dispatch of the FP32 smoother on the 512^3 film + 32 drops workload
-# (average over all levels, the unit of the roofline figure), from two rocprofv3 PMC
-# passes over one step: FETCH_SIZE and WRITE_SIZE in KiB, scaled by what the same
-# counters read for a plain 1 GiB device copy (x2.0 and x1.0 on this part).  Valid
-# only for the kernel sources they were taken on: the hash below is recomputed at
-# run time and the figure is dropped (null) once the sources differ.
+# HBM bytes per dispatch of the FP32 two-sweep smoother on the 512^3 film + 32
+# drops workload (average over all levels, the unit of the roofline figure), from
+# two rocprofv3 PMC passes over one step: FETCH_SIZE and WRITE_SIZE in KiB, scaled
+# by what the same counters read for a plain 1 GiB device copy (x2.0 and x1.0 on
+# this part).  Valid only for the kernel sources they were taken on: the hash
+# below is recomputed at run time and the figure is dropped (null) once the
+# sources differ.
 TRAFFIC = {
-    "kernel": "mgp::k_sweep_fused<float, 8>",
+    "kernel": "mgp::k_sweep2_fused<float, 16>",
     "n": 512,
-    "sources": ["mgp_sweep.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp"],
-    "sha256": "d7d7dcde9e9067df71e389b25bc1eb570be4ee6c6360ce9ecb602469a5d23ac4",
-    "fetch_kib": 481623.6275390625,
-    "write_kib": 149760.0,
+    "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp"],
+    "sha256": "b4739aa18b5ebce5a86416b9af31de23270d30a051d880b654109921317f4d34",
+    "fetch_kib": 409979.48828125,
+    "write_kib": 149760.0376953125,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
@@ -93,6 +94,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solves")
+    ap.add_argument("--no-fcg", action="store_true", help="skip the flexible-CG variant solves")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: all available)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (scales PMC byte counters)")
@@ -252,6 +254,28 @@ def main() -> int:
             del p64
         log(f"fp64 solve {fp64['time_to_tol_ms']:.2f} ms, {fp64['cycles']} cycles")
 
+    # Krylov-accelerated variant (flexible CG, one V-cycle per iteration): reported
+    # beside the headline V-cycle solve, not as the headline
+    fcg = None
+    if not args.no_fcg:
+        fcg = {}
+        for prec in ("mixed", "fp64"):
+            with S.Solver(*beta, wl.h, precision=prec, zero_guess=True, method="fcg") as sf:
+                pf = torch.zeros_like(rhs)
+                sf.solve(rhs, args.tol, p=pf)
+                times, stf = [], None
+                for _ in range(max(1, args.steps)):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    _, stf = sf.solve(rhs, args.tol, p=pf)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    times.append(e0.elapsed_time(e1))
+                fcg[prec] = {"time_to_tol_ms": statistics.median(times), "iterations": stf.cycles,
+                             "rel_res": stf.rel_res}
+                del pf
+            log(f"fcg {prec} solve {fcg[prec]['time_to_tol_ms']:.2f} ms, {fcg[prec]['iterations']} iterations")
+
     roofline = None
     if dominant:
         d = ksum[dominant]
@@ -288,6 +312,7 @@ def main() -> int:
                   **smoother_figures(ksum, cells),
                   "kernels": ksum},
         "fp64": fp64,
+        "fcg": fcg,
         "phases_ms": {k: statistics.median(v) for k, v in phases.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -21,8 +21,8 @@
 // Each thread owns one pair of x-adjacent cells of the tile + 4-cell ring
 // (36 pairs per row, TY + 8 rows): in every plane one cell of the pair is an
 // A-cell and the other a B-cell.  The coefficients of the pair's cells are
-// loaded once per plane, one step before first use, and kept in registers
-// for the five steps during which the four stages visit that plane.  The
+// loaded once per plane, two steps before first full use, and kept in
+// registers for the steps during which the four stages visit that plane.  The
 // previous iterate is read once and the result written once: the memory
 // traffic of one sweep for two sweeps of work, plus the ring re-reads.
 #pragma once
@@ -99,24 +99,27 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
             s[lo] = v.y;
         }
     };
-    // coefficients of the pair in one plane; bz is the pair's lower z-face
+    // coefficients of the pair in one plane: lower z-faces (loaded first: the
+    // stage one plane down needs them as its upper faces one step earlier than
+    // the rest), rhs, x-faces (3), y-faces below and above
     struct Coef {
-        T2 b, bx, by, byu, bz;
+        T2 bz, b, bx, by, byu;
         T bxn;
     };
     auto load_coef = [&](int z, Coef& C) {
         const unsigned zz = cpl(z);
+        // z-faces have nz + 1 planes: plane nz is the top wall (0)
+        C.bz = bload2<T>(r_bz, oc, (unsigned)min(max(z, 0), d.nz) * psz);
         C.b = bload2<T>(r_b, oc, zz * psz);
         C.bx = bload2<T>(r_bx, ofx, zz * pfx);
         C.bxn = bload1<T>(r_bx, ofx, zz * pfx + 2u * sizeof(T));
         C.by = bload2<T>(r_by, oc, zz * pfy);
         C.byu = bload2<T>(r_by, oc, zz * pfy + rowb);
     };
-    auto load_bz = [&](int z) -> T2 { return bload2<T>(r_bz, oc, (unsigned)min(max(z, 0), d.nz) * psz); };
 
     // Half-sweep of the colour-`col` cell of the pair on plane z, if that cell
     // lies in the tile + r ring and in the domain; the value goes to `v`.
-    auto relax = [&](int z, int col, int r, const Coef& C, T2 bzu, bool& ok, int& li, T& v) {
+    auto relax = [&](int z, int col, int r, const Coef& C, const Coef& Cup, bool& ok, int& li, T& v) {
         const int odd = (gx0 + gy + z + col) & 1;
         const int gx = gx0 + odd;
         ok = inside && z >= 0 && z < d.nz && gx >= x0 - r && gx < x0 + G::TX + r && gx < d.nx && gy >= y0 - r &&
@@ -132,7 +135,7 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         const T byl = odd ? C.by.y : C.by.x;
         const T byh = odd ? C.byu.y : C.byu.x;
         const T bzl = odd ? C.bz.y : C.bz.x;
-        const T bzh = odd ? bzu.y : bzu.x;
+        const T bzh = odd ? Cup.bz.y : Cup.bz.x;
         const T b = odd ? C.b.y : C.b.x;
         T dg = bxl, of = bxl * S[G::idx(ex - 1, pyi)];
         dg += bxh; of += bxh * S[G::idx(ex + 1, pyi)];
@@ -145,40 +148,36 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
 
     const int cA = c0, cB = 1 - c0;
     const int sbeg = z0 - 3, send = z1 + 3;
-    store_in(sbeg - 1, load_in(sbeg - 1));
-    store_in(sbeg, load_in(sbeg));
-    T2 v = load_in(sbeg + 1);
-    Coef C0, C1, C2, C3, C4, Cn;
-    load_coef(sbeg, C0);
-    C0.bz = load_bz(sbeg);
-    T2 zn = load_bz(sbeg + 1);
-    C1 = C0;
-    C2 = C0;
-    C3 = C0;
-    C4 = C0;
     const bool core = active && pxi >= 2 && pxi < 2 + G::HX - 4 && pyi >= 4 && pyi < 4 + TY && gy < d.ny &&
                       gx0 < d.nx;
+    T2 v;
 
-    for (int s = sbeg; s <= send; ++s) {
+    // One z-step.  The coefficients of plane z live in set R[(z - sbeg) mod 7]:
+    // a step loads plane s+2's set (two steps before its first full use) into
+    // the set of plane s-5, which no stage needs any more, so the seven sets
+    // rotate by name (the loop is unrolled seven times).  A stage on plane z
+    // takes its upper z-faces from the set of plane z+1.  The iterate of plane
+    // s+2 is loaded first in the step and written to LDS at the next step.
+    auto step = [&](int s, Coef& Ln, const Coef& Cp1, const Coef& Cs, const Coef& Cm1, const Coef& Cm2,
+                    const Coef& Cm3, const Coef& Cm4) {
         store_in(s + 1, v);
         v = load_in(s + 2);
-        load_coef(s + 1, Cn);
-        const T2 zn2 = load_bz(s + 2);
+        load_coef(s + 2, Ln);
         lds_barrier();
         // phase 1: A1 on plane s, B2 on plane s-4 (written to memory)
         if (s <= z1 + 2) {
             bool ok;
             int li;
-            T a;
-            relax(s, cA, 3, C0, zn, ok, li, a);
+            T a = (T)0;
+            relax(s, cA, 3, Cs, Cp1, ok, li, a);
             if (ok) slot[(s & (G::SLOTS - 1)) * G::PLANE + li] = a;
         }
         const int zb = s - 4;
         if (zb >= z0 && core) {
             bool ok;
             int li;
-            T bv;
-            relax(zb, cB, 0, C4, C3.bz, ok, li, bv);
+            T bv = (T)0;
+            relax(zb, cB, 0, Cm4, Cm3, ok, li, bv);
             const T* S = slot + (zb & (G::SLOTS - 1)) * G::PLANE;
             const bool bodd = li == lo;
             const T av = S[bodd ? le : lo];
@@ -192,8 +191,8 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         if (s - 1 >= z0 - 2 && s - 1 <= z1 + 1) {
             bool ok;
             int li;
-            T bv;
-            relax(s - 1, cB, 2, C1, C0.bz, ok, li, bv);
+            T bv = (T)0;
+            relax(s - 1, cB, 2, Cm1, Cs, ok, li, bv);
             if (ok) slot[((s - 1) & (G::SLOTS - 1)) * G::PLANE + li] = bv;
         }
         lds_barrier();
@@ -201,23 +200,42 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         if (s - 2 >= z0 - 1 && s - 2 <= z1) {
             bool ok;
             int li;
-            T a;
-            relax(s - 2, cA, 1, C2, C1.bz, ok, li, a);
+            T a = (T)0;
+            relax(s - 2, cA, 1, Cm2, Cm1, ok, li, a);
             if (ok) slot[((s - 2) & (G::SLOTS - 1)) * G::PLANE + li] = a;
         }
-        C4 = C3;
-        C3 = C2;
-        C2 = C1;
-        C1 = C0;
-        C0 = Cn;
-        C0.bz = zn;
-        zn = zn2;
+    };
+
+    store_in(sbeg - 1, load_in(sbeg - 1));
+    store_in(sbeg, load_in(sbeg));
+    v = load_in(sbeg + 1);
+    Coef R0, R1, R2, R3, R4, R5, R6;
+    load_coef(sbeg, R0);
+    load_coef(sbeg + 1, R1);
+    R2 = R3 = R4 = R5 = R6 = R0;
+    // step(s, Ln = set(s+2), set(s+1), set(s), set(s-1), set(s-2), set(s-3), set(s-4))
+    for (int s = sbeg; s <= send; s += 7) {
+        step(s, R2, R1, R0, R6, R5, R4, R3);
+        if (s + 1 > send) break;
+        step(s + 1, R3, R2, R1, R0, R6, R5, R4);
+        if (s + 2 > send) break;
+        step(s + 2, R4, R3, R2, R1, R0, R6, R5);
+        if (s + 3 > send) break;
+        step(s + 3, R5, R4, R3, R2, R1, R0, R6);
+        if (s + 4 > send) break;
+        step(s + 4, R6, R5, R4, R3, R2, R1, R0);
+        if (s + 5 > send) break;
+        step(s + 5, R0, R6, R5, R4, R3, R2, R1);
+        if (s + 6 > send) break;
+        step(s + 6, R1, R0, R6, R5, R4, R3, R2);
     }
 }
 
-// Blocks of the two-sweep kernel: z is cut into chunks of at least 32 planes
-// (each chunk re-walks 7 planes of stage lag) so that the grid holds about
-// 1024 blocks.
+// Blocks of the two-sweep kernel: z is cut into chunks so that the grid holds
+// about 256 blocks, one per compute unit (one block of 14 waves fills a CU),
+// with at least 8 planes per chunk (each chunk re-walks 7 planes of stage
+// lag).  Measured on 64^3..512^3 grids, fewer and longer chunks beat more
+// and shorter ones down to one block per CU.
 struct Sweep2Launch {
     int ntx, nty, zc, blocks;
 };
@@ -229,9 +247,9 @@ inline Sweep2Launch sweep2_geom(const Dims& d)
     g.ntx = (d.nx + 63) / 64;
     g.nty = (d.ny + TY - 1) / TY;
     const int tiles = g.ntx * g.nty;
-    int nzc = (1024 + tiles - 1) / tiles;
+    int nzc = (256 + tiles - 1) / tiles;
     int zc = (d.nz + nzc - 1) / nzc;
-    if (zc < 32) zc = 32;
+    if (zc < 8) zc = 8;
     if (zc > d.nz) zc = d.nz;
     g.zc = zc;
     g.blocks = tiles * ((d.nz + zc - 1) / zc);

@@ -13,10 +13,10 @@
 // A1(s) and B2(s-4) touch disjoint planes, so they share a phase.  The rings
 // shrink by one cell per stage, so every value a tile cell needs is computed
 // inside the block: no block waits for another.  Every plane holds the newest
-// value of each of its cells in one LDS slot (8 slots cover planes s-5..s+1
-// plus the one being filled); stage order within a step guarantees that each
-// read sees the state it needs (e.g. B1(s-1) reads A-cells of s-2 before A2
-// overwrites them in the same step).
+// value of each of its cells in one LDS slot (7 slots cover planes s-5..s+1;
+// plane s+1 goes into the slot of plane s-6); stage order within a step
+// guarantees that each read sees the state it needs (e.g. B1(s-1) reads
+// A-cells of s-2 before A2 overwrites them in the same step).
 //
 // Each thread owns one pair of x-adjacent cells of the tile + 4-cell ring
 // (36 pairs per row, TY + 8 rows): in every plane one cell of the pair is an
@@ -26,6 +26,8 @@
 // previous iterate is read once and the result written once: the memory
 // traffic of one sweep for two sweeps of work, plus the ring re-reads.
 #pragma once
+
+#include <type_traits>
 
 #include "mgp_buffer.hpp"
 
@@ -40,7 +42,7 @@ struct Sweep2Geom {
     static constexpr int NP = HX * EY;         // pairs per plane = working threads
     static constexpr int NT = (NP + 63) / 64 * 64;
     static constexpr int PLANE = EX * EY;
-    static constexpr int SLOTS = 8;
+    static constexpr int SLOTS = 7;         // planes s-5 .. s+1 of step s
     // LDS position of plane coordinates (ex, ey): each row keeps its even-x
     // cells, then its odd-x cells (one colour of a row is contiguous).
     __device__ static int idx(int ex, int ey) { return ey * EX + (ex & 1) * HX + (ex >> 1); }
@@ -92,11 +94,13 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         const bool zv = !zero_in && z >= 0 && z < d.nz;
         return bload2<T>(zv ? r_in : r_null, oin, cpl(z) * psz);
     };
-    auto store_in = [&](int z, T2 v) {
+    // LDS plane of z-step position K (0..6) and plane offset dz from the step's
+    // plane s: the loop is unrolled seven times, so slot numbers are constants
+    auto plane = [&](int K, int dz) -> T* { return slot + ((K + dz + 7 * 7) % 7) * G::PLANE; };
+    auto store_in = [&](T* P, T2 v) {
         if (active) {
-            T* s = slot + (z & (G::SLOTS - 1)) * G::PLANE;
-            s[le] = v.x;
-            s[lo] = v.y;
+            P[le] = v.x;
+            P[lo] = v.y;
         }
     };
     // coefficients of the pair in one plane: lower z-faces (loaded first: the
@@ -117,19 +121,30 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         C.byu = bload2<T>(r_by, oc, zz * pfy + rowb);
     };
 
-    // Half-sweep of the colour-`col` cell of the pair on plane z, if that cell
-    // lies in the tile + r ring and in the domain; the value goes to `v`.
-    auto relax = [&](int z, int col, int r, const Coef& C, const Coef& Cup, bool& ok, int& li, T& v) {
-        const int odd = (gx0 + gy + z + col) & 1;
-        const int gx = gx0 + odd;
-        ok = inside && z >= 0 && z < d.nz && gx >= x0 - r && gx < x0 + G::TX + r && gx < d.nx && gy >= y0 - r &&
-             gy < y0 + TY + r;
-        const int ex = 2 * pxi + odd;
+    // Which cell of the pair a stage relaxes, and whether it lies in the
+    // stage's ring: bit 2r + o of `ring` says cell o (0 even x, 1 odd x) of
+    // this thread's pair is in the tile + r ring and in the domain.
+    int ring = 0;
+    for (int r = 0; r <= 3; ++r)
+        for (int o = 0; o <= 1; ++o) {
+            const int gx = gx0 + o;
+            const bool in_r = inside && gx >= x0 - r && gx < x0 + G::TX + r && gx < d.nx && gy >= y0 - r &&
+                              gy < y0 + TY + r;
+            ring |= (in_r ? 1 : 0) << (2 * r + o);
+        }
+    const int gyp = gy & 1;  // the pair starts at even x: cell parity is (gy + z) & 1 plus the cell index
+
+    // Half-sweep of the colour-`col` cell of the pair on plane z (LDS planes
+    // Pm, P0, Pp hold z-1, z, z+1), if that cell lies in the tile + r ring and
+    // in the domain; the value goes to `v`, its LDS index to `li`.
+    auto relax = [&](int z, int col, int r, const T* Pm, const T* P0, const T* Pp, const Coef& C, const Coef& Cup,
+                     bool& ok, int& li, T& v) {
+        const int odd = gyp ^ ((z + col) & 1);
+        ok = z >= 0 && z < d.nz && ((ring >> (2 * r + odd)) & 1);
         li = odd ? lo : le;
         if (!ok) return;
-        const T* S = slot + (z & (G::SLOTS - 1)) * G::PLANE;
-        const T* Sm = slot + ((z - 1) & (G::SLOTS - 1)) * G::PLANE;
-        const T* Sp = slot + ((z + 1) & (G::SLOTS - 1)) * G::PLANE;
+        // x-neighbours: (even cell) odd cells x-1, x+1 = lo-1, lo; (odd cell) even cells le, le+1
+        const int xm = odd ? le : lo - 1;
         const T bxl = odd ? C.bx.y : C.bx.x;
         const T bxh = odd ? C.bxn : C.bx.y;
         const T byl = odd ? C.by.y : C.by.x;
@@ -137,12 +152,12 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         const T bzl = odd ? C.bz.y : C.bz.x;
         const T bzh = odd ? Cup.bz.y : Cup.bz.x;
         const T b = odd ? C.b.y : C.b.x;
-        T dg = bxl, of = bxl * S[G::idx(ex - 1, pyi)];
-        dg += bxh; of += bxh * S[G::idx(ex + 1, pyi)];
-        dg += byl; of += byl * S[G::idx(ex, pyi - 1)];
-        dg += byh; of += byh * S[G::idx(ex, pyi + 1)];
-        dg += bzl; of += bzl * Sm[li];
-        dg += bzh; of += bzh * Sp[li];
+        T dg = bxl, of = bxl * P0[xm];
+        dg += bxh; of += bxh * P0[xm + 1];
+        dg += byl; of += byl * P0[li - G::EX];
+        dg += byh; of += byh * P0[li + G::EX];
+        dg += bzl; of += bzl * Pm[li];
+        dg += bzh; of += bzh * Pp[li];
         v = quot(of - h2 * b, dg);
     };
 
@@ -150,17 +165,18 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     const int sbeg = z0 - 3, send = z1 + 3;
     const bool core = active && pxi >= 2 && pxi < 2 + G::HX - 4 && pyi >= 4 && pyi < 4 + TY && gy < d.ny &&
                       gx0 < d.nx;
-    T2 v;
 
-    // One z-step.  The coefficients of plane z live in set R[(z - sbeg) mod 7]:
-    // a step loads plane s+2's set (two steps before its first full use) into
-    // the set of plane s-5, which no stage needs any more, so the seven sets
-    // rotate by name (the loop is unrolled seven times).  A stage on plane z
-    // takes its upper z-faces from the set of plane z+1.  The iterate of plane
-    // s+2 is loaded first in the step and written to LDS at the next step.
-    auto step = [&](int s, Coef& Ln, const Coef& Cp1, const Coef& Cs, const Coef& Cm1, const Coef& Cm2,
+    // One z-step at unroll position K = (s - sbeg) mod 7.  The coefficients of
+    // plane z live in set R[(z - sbeg) mod 7]: a step loads plane s+2's set
+    // (two steps before its first full use) into the set of plane s-5, which no
+    // stage needs any more, so the seven sets rotate by name.  A stage on plane
+    // z takes its upper z-faces from the set of plane z+1.  The iterate of
+    // plane s+2 is loaded first in the step and written to LDS at the next step.
+    T2 v;
+    auto step = [&](auto Kc, int s, Coef& Ln, const Coef& Cp1, const Coef& Cs, const Coef& Cm1, const Coef& Cm2,
                     const Coef& Cm3, const Coef& Cm4) {
-        store_in(s + 1, v);
+        constexpr int K = decltype(Kc)::value;
+        store_in(plane(K, 1), v);
         v = load_in(s + 2);
         load_coef(s + 2, Ln);
         lds_barrier();
@@ -169,18 +185,17 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
             bool ok;
             int li;
             T a = (T)0;
-            relax(s, cA, 3, Cs, Cp1, ok, li, a);
-            if (ok) slot[(s & (G::SLOTS - 1)) * G::PLANE + li] = a;
+            relax(s, cA, 3, plane(K, -1), plane(K, 0), plane(K, 1), Cs, Cp1, ok, li, a);
+            if (ok) plane(K, 0)[li] = a;
         }
         const int zb = s - 4;
         if (zb >= z0 && core) {
             bool ok;
             int li;
             T bv = (T)0;
-            relax(zb, cB, 0, Cm4, Cm3, ok, li, bv);
-            const T* S = slot + (zb & (G::SLOTS - 1)) * G::PLANE;
+            relax(zb, cB, 0, plane(K, -5), plane(K, -4), plane(K, -3), Cm4, Cm3, ok, li, bv);
             const bool bodd = li == lo;
-            const T av = S[bodd ? le : lo];
+            const T av = plane(K, -4)[bodd ? le : lo];
             T2 o;
             o.x = bodd ? av : bv;
             o.y = bodd ? bv : av;
@@ -192,8 +207,8 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
             bool ok;
             int li;
             T bv = (T)0;
-            relax(s - 1, cB, 2, Cm1, Cs, ok, li, bv);
-            if (ok) slot[((s - 1) & (G::SLOTS - 1)) * G::PLANE + li] = bv;
+            relax(s - 1, cB, 2, plane(K, -2), plane(K, -1), plane(K, 0), Cm1, Cs, ok, li, bv);
+            if (ok) plane(K, -1)[li] = bv;
         }
         lds_barrier();
         // phase 3: A2 on plane s-2
@@ -201,33 +216,40 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
             bool ok;
             int li;
             T a = (T)0;
-            relax(s - 2, cA, 1, Cm2, Cm1, ok, li, a);
-            if (ok) slot[((s - 2) & (G::SLOTS - 1)) * G::PLANE + li] = a;
+            relax(s - 2, cA, 1, plane(K, -3), plane(K, -2), plane(K, -1), Cm2, Cm1, ok, li, a);
+            if (ok) plane(K, -2)[li] = a;
         }
     };
 
-    store_in(sbeg - 1, load_in(sbeg - 1));
-    store_in(sbeg, load_in(sbeg));
+    store_in(plane(0, -1), load_in(sbeg - 1));
+    store_in(plane(0, 0), load_in(sbeg));
     v = load_in(sbeg + 1);
     Coef R0, R1, R2, R3, R4, R5, R6;
     load_coef(sbeg, R0);
     load_coef(sbeg + 1, R1);
     R2 = R3 = R4 = R5 = R6 = R0;
-    // step(s, Ln = set(s+2), set(s+1), set(s), set(s-1), set(s-2), set(s-3), set(s-4))
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
+    using I6 = std::integral_constant<int, 6>;
+    // step(K, s, Ln = set(s+2), set(s+1), set(s), set(s-1), set(s-2), set(s-3), set(s-4))
     for (int s = sbeg; s <= send; s += 7) {
-        step(s, R2, R1, R0, R6, R5, R4, R3);
+        step(I0{}, s, R2, R1, R0, R6, R5, R4, R3);
         if (s + 1 > send) break;
-        step(s + 1, R3, R2, R1, R0, R6, R5, R4);
+        step(I1{}, s + 1, R3, R2, R1, R0, R6, R5, R4);
         if (s + 2 > send) break;
-        step(s + 2, R4, R3, R2, R1, R0, R6, R5);
+        step(I2{}, s + 2, R4, R3, R2, R1, R0, R6, R5);
         if (s + 3 > send) break;
-        step(s + 3, R5, R4, R3, R2, R1, R0, R6);
+        step(I3{}, s + 3, R5, R4, R3, R2, R1, R0, R6);
         if (s + 4 > send) break;
-        step(s + 4, R6, R5, R4, R3, R2, R1, R0);
+        step(I4{}, s + 4, R6, R5, R4, R3, R2, R1, R0);
         if (s + 5 > send) break;
-        step(s + 5, R0, R6, R5, R4, R3, R2, R1);
+        step(I5{}, s + 5, R0, R6, R5, R4, R3, R2, R1);
         if (s + 6 > send) break;
-        step(s + 6, R1, R0, R6, R5, R4, R3, R2);
+        step(I6{}, s + 6, R1, R0, R6, R5, R4, R3, R2);
     }
 }
 

@@ -6,11 +6,12 @@
 // A half-sweep of a cell reads only its six face neighbours, which have the
 // other colour, so a stage on plane z needs the previous stage on planes
 // z-1, z, z+1.  A block that owns a 64 x TY tile of (x, y) marches a chunk of
-// z with the stages staggered in z, per step s (three LDS barriers):
-//   phase 1: A1 on plane s   (tile + 3-cell ring)   and   B2 on plane s-4 (tile)
-//   phase 2: B1 on plane s-1 (tile + 2-cell ring)
-//   phase 3: A2 on plane s-2 (tile + 1-cell ring)
-// A1(s) and B2(s-4) touch disjoint planes, so they share a phase.  The rings
+// z with the stages staggered in z, per step s (two LDS barriers):
+//   phase 1: A1 on plane s   (tile + 3-cell ring)  and  A2 on plane s-3 (tile + 1-cell ring)
+//   phase 2: B1 on plane s-1 (tile + 2-cell ring)  and  B2 on plane s-4 (tile)
+// The two stages of a phase touch disjoint planes and states: A2(s-3) needs
+// B1 up to plane s-2 (done a step earlier), B2(s-4) needs A2 up to s-3 (done
+// in phase 1), and B1(s-1) still finds plane s-2's A-cells in state A1.  The rings
 // shrink by one cell per stage, so every value a tile cell needs is computed
 // inside the block: no block waits for another.  Every plane holds the newest
 // value of each of its cells in one LDS slot (7 slots cover planes s-5..s+1;
@@ -180,13 +181,29 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         v = load_in(s + 2);
         load_coef(s + 2, Ln);
         lds_barrier();
-        // phase 1: A1 on plane s, B2 on plane s-4 (written to memory)
+        // phase 1: A1 on plane s and A2 on plane s-3 (disjoint planes and states)
         if (s <= z1 + 2) {
             bool ok;
             int li;
             T a = (T)0;
             relax(s, cA, 3, plane(K, -1), plane(K, 0), plane(K, 1), Cs, Cp1, ok, li, a);
             if (ok) plane(K, 0)[li] = a;
+        }
+        if (s - 3 >= z0 - 1 && s - 3 <= z1) {
+            bool ok;
+            int li;
+            T a = (T)0;
+            relax(s - 3, cA, 1, plane(K, -4), plane(K, -3), plane(K, -2), Cm3, Cm2, ok, li, a);
+            if (ok) plane(K, -3)[li] = a;
+        }
+        lds_barrier();
+        // phase 2: B1 on plane s-1 and B2 on plane s-4 (B2 written to memory)
+        if (s - 1 >= z0 - 2 && s - 1 <= z1 + 1) {
+            bool ok;
+            int li;
+            T bv = (T)0;
+            relax(s - 1, cB, 2, plane(K, -2), plane(K, -1), plane(K, 0), Cm1, Cs, ok, li, bv);
+            if (ok) plane(K, -1)[li] = bv;
         }
         const int zb = s - 4;
         if (zb >= z0 && core) {
@@ -200,24 +217,6 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
             o.x = bodd ? av : bv;
             o.y = bodd ? bv : av;
             *reinterpret_cast<T2*>(out + (long)zb * d.nx * d.ny + (long)gy * d.nx + gx0) = o;
-        }
-        lds_barrier();
-        // phase 2: B1 on plane s-1
-        if (s - 1 >= z0 - 2 && s - 1 <= z1 + 1) {
-            bool ok;
-            int li;
-            T bv = (T)0;
-            relax(s - 1, cB, 2, plane(K, -2), plane(K, -1), plane(K, 0), Cm1, Cs, ok, li, bv);
-            if (ok) plane(K, -1)[li] = bv;
-        }
-        lds_barrier();
-        // phase 3: A2 on plane s-2
-        if (s - 2 >= z0 - 1 && s - 2 <= z1) {
-            bool ok;
-            int li;
-            T a = (T)0;
-            relax(s - 2, cA, 1, plane(K, -3), plane(K, -2), plane(K, -1), Cm2, Cm1, ok, li, a);
-            if (ok) plane(K, -2)[li] = a;
         }
     };
 

@@ -58,9 +58,9 @@ TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp"],
-    "sha256": "b4739aa18b5ebce5a86416b9af31de23270d30a051d880b654109921317f4d34",
-    "fetch_kib": 409979.48828125,
-    "write_kib": 149760.0376953125,
+    "sha256": "9220d93dd2b7cf43a004c1012c1b169df9bcd363ad3aef47269dec7e73793687",
+    "fetch_kib": 404067.31640625,
+    "write_kib": 149763.85166015624,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

@@ -55,7 +55,8 @@ struct mg_ctx {
     double* ptmp = nullptr;      // ping-pong partner of the caller's p
     double* work = nullptr;      // scratch (coarse inverse build; verification copies)
     double* fr = nullptr;        // flexible-CG residual, direction and L direction (MG_FLAG_FCG)
-    double* fd = nullptr;
+    double* fd = nullptr;        // current direction: one of fd_buf
+    double* fd_buf[2] = {nullptr, nullptr};
     double* fq = nullptr;
     double* partials = nullptr;  // kReduceBlocks
     double* scal = nullptr;      // device scalars
@@ -409,14 +410,29 @@ int fcg_step(mg_ctx* c, const TZ* z, double* x, float* r32, bool first, double d
         CHECK_LAUNCH(c);
         TRY(reduce_to(c, kReduceBlocks, kSlotZQ));
     }
-    k_fcg_direction<TZ><<<grid_for(n), kBlock, 0, c->stream>>>(z, c->fd, n, c->scal, kSlotZQ, dq_prev,
-                                                                first ? 1 : 0);
-    CHECK_LAUNCH(c);
-    k_fcg_apply<<<kReduceBlocks, kBlock, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, F.d, 1.0 / (F.h * F.h),
-                                                         c->fd, c->fr, c->fq, c->partials);
-    CHECK_LAUNCH(c);
-    TRY(reduce_to(c, kReduceBlocks, kSlotDQ));
-    k_reduce_final<<<1, kBlock, 0, c->stream>>>(c->partials + kReduceBlocks, kReduceBlocks, c->scal, kSlotDR);
+    int nparts = kReduceBlocks;
+    if (res_tiled_ok(F.d, sizeof(double)) && 2 * res_geom(F.d).blocks <= kMaxPartials) {
+        // d = z - gamma d_prev and q = L d in one tiled pass; d ping-pongs
+        // between two buffers because its ring is re-formed from d_prev
+        const ResGeom g = res_geom(F.d);
+        nparts = g.blocks;
+        double* dnew = c->fd == c->fd_buf[0] ? c->fd_buf[1] : c->fd_buf[0];
+        k_fcg_dir_apply<TZ><<<g.blocks, kResNT, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, z, c->fd, c->fr, F.d,
+                                                                 1.0 / (F.h * F.h), c->scal, kSlotZQ, dq_prev,
+                                                                 first ? 1 : 0, g.zc, g.ntx, g.nty, dnew, c->fq,
+                                                                 c->partials);
+        CHECK_LAUNCH(c);
+        c->fd = dnew;
+    } else {
+        k_fcg_direction<TZ><<<grid_for(n), kBlock, 0, c->stream>>>(z, c->fd, n, c->scal, kSlotZQ, dq_prev,
+                                                                    first ? 1 : 0);
+        CHECK_LAUNCH(c);
+        k_fcg_apply<<<kReduceBlocks, kBlock, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, F.d, 1.0 / (F.h * F.h),
+                                                             c->fd, c->fr, c->fq, c->partials);
+        CHECK_LAUNCH(c);
+    }
+    TRY(reduce_to(c, nparts, kSlotDQ));
+    k_reduce_final<<<1, kBlock, 0, c->stream>>>(c->partials + nparts, nparts, c->scal, kSlotDR);
     CHECK_LAUNCH(c);
     k_fcg_update<<<kReduceBlocks, kBlock, 0, c->stream>>>(x, c->fr, c->fd, c->fq, n, c->scal, kSlotDR, kSlotDQ,
                                                           r32, c->partials);
@@ -681,7 +697,9 @@ void carve(mg_ctx* c, Arena& a)
     c->scal = a.take<double>(16);
     if (c->opts.flags & MG_FLAG_FCG) {
         c->fr = a.take<double>(n0);
-        c->fd = a.take<double>(n0);
+        c->fd_buf[0] = a.take<double>(n0);
+        c->fd_buf[1] = a.take<double>(n0);
+        c->fd = c->fd_buf[0];
         c->fq = a.take<double>(n0);
     }
     for (int l = 0; l < c->nlev; ++l) {

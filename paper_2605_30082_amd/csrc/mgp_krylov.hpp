@@ -11,6 +11,7 @@
 #pragma once
 
 #include "mgp_kernels.hpp"
+#include "mgp_resid.hpp"
 
 namespace mgp {
 
@@ -80,6 +81,161 @@ __global__ void k_fcg_update(double* __restrict__ x, double* __restrict__ r, con
         acc += rc * rc;
     }
     block_partial(acc, partials);
+}
+
+// The direction update and q = L d in one tiled pass (the tiling of k_resid:
+// 64 x 8 tiles marching in z, one LDS plane per step): while a plane of d is
+// staged into LDS it is formed as z - gamma d_prev (gamma = scal[zq_slot] /
+// dq_prev; first: d = z), with its 1-cell ring recomputed rather than
+// exchanged.  Each thread writes d and q for its pair and accumulates (d, q)
+// into partials[0, gridDim) and (d, r) into partials[gridDim, 2 gridDim).
+template <typename TZ>
+__global__ void __launch_bounds__(kResNT)
+k_fcg_dir_apply(const double* __restrict__ bx, const double* __restrict__ by, const double* __restrict__ bz,
+                const TZ* __restrict__ zv, const double* __restrict__ dprev, const double* __restrict__ r, Dims d,
+                double inv_h2, const double* __restrict__ scal, int zq_slot, double dq_prev, int first, int zc,
+                int ntx, int nty, double* __restrict__ dout, double* __restrict__ q, double* __restrict__ partials)
+{
+    using T = double;
+    using T2 = double2;
+    __shared__ T slot[4 * kResPlane];
+    __shared__ double ws[kResNT / 64];
+
+    const int nb = (int)gridDim.x, bid = (int)blockIdx.x;
+    const int q8 = nb / 8, r8 = nb % 8, xcd = bid % 8;
+    const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / 8;
+    const int tx = logical % ntx, ty = (logical / ntx) % nty, tz = logical / (ntx * nty);
+    const int x0 = tx * 64, y0 = ty * kResTY, z0 = tz * zc;
+    const int z1 = min(z0 + zc, d.nz);
+    const double gamma = first ? 0.0 : scal[zq_slot] / dq_prev;
+
+    const int t = (int)threadIdx.x;
+    const int row = t >> 5, k = t & 31;
+    const int y = y0 + row, xp = x0 + 2 * k;
+    const bool mine = y < d.ny && xp < d.nx;
+    const int yc = min(y, d.ny - 1), xc = min(xp, d.nx - 2);
+
+    const unsigned psz = (unsigned)((long)d.nx * d.ny * sizeof(T));
+    const unsigned pszz = (unsigned)((long)d.nx * d.ny * sizeof(TZ));
+    const unsigned pfx = (unsigned)((long)(d.nx + 2) * d.ny * sizeof(T));
+    const unsigned pfy = (unsigned)((long)d.nx * (d.ny + 1) * sizeof(T));
+    const unsigned rowb = (unsigned)(d.nx * sizeof(T));
+    const long ncell = (long)d.nx * d.ny * d.nz;
+    const auto r_r = make_rsrc(r, (unsigned)(ncell * sizeof(T)));
+    const auto r_bx = make_rsrc(bx, (unsigned)(n_fx(d) * sizeof(T)));
+    const auto r_by = make_rsrc(by, (unsigned)(n_fy(d) * sizeof(T)));
+    const auto r_bz = make_rsrc(bz, (unsigned)(n_fz(d) * sizeof(T)));
+    const auto r_z = make_rsrc(zv, (unsigned)(ncell * sizeof(TZ)));
+    const auto r_dp = make_rsrc(dprev, first ? 0u : (unsigned)(ncell * sizeof(T)));
+    const auto r_null = make_rsrc(zv, 0u);
+
+    const unsigned oc = (unsigned)(yc * d.nx + xc) * sizeof(T);
+    const unsigned ofx = (unsigned)(yc * (d.nx + 2) + xc) * sizeof(T);
+    unsigned loff[kResLoads], loffz[kResLoads];
+    int lidx[kResLoads];
+#pragma unroll
+    for (int j = 0; j < kResLoads; ++j) {
+        const int f = t + j * kResNT;
+        loff[j] = loffz[j] = kOutside;
+        lidx[j] = -1;
+        if (f < 66 * kResEY) {
+            const int ey = f / 66, ex = f - ey * 66;
+            const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+            lidx[j] = ey * kResEX + ex + 1;
+            if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny) {
+                loff[j] = (unsigned)(gy * d.nx + gx) * sizeof(T);
+                loffz[j] = (unsigned)(gy * d.nx + gx) * sizeof(TZ);
+            }
+        }
+    }
+    auto cplane = [&](int zz) { return (unsigned)min(max(zz, 0), d.nz - 1); };
+    // plane of d = z - gamma d_prev (0 outside the domain)
+    auto load_plane = [&](int zz, T* v) {
+        const bool in = zz >= 0 && zz < d.nz;
+        const auto rz = in ? r_z : r_null;
+        const auto rd = in ? r_dp : r_null;
+#pragma unroll
+        for (int j = 0; j < kResLoads; ++j)
+            v[j] = (T)bload1<TZ>(rz, loffz[j], cplane(zz) * pszz) - gamma * bload1<T>(rd, loff[j], cplane(zz) * psz);
+    };
+    auto store_plane = [&](int zz, const T* v) {
+        T* sl = slot + (zz & 3) * kResPlane;
+#pragma unroll
+        for (int j = 0; j < kResLoads; ++j)
+            if (lidx[j] >= 0) sl[lidx[j]] = v[j];
+    };
+    struct Coef {
+        T2 r, bx, by, byu, bzh;
+        T bxn;
+    };
+    auto load_coef = [&](int zz, Coef& C) {
+        const unsigned zp = cplane(zz);
+        C.r = bload2<T>(r_r, oc, zp * psz);
+        C.bx = bload2<T>(r_bx, ofx, zp * pfx);
+        C.bxn = bload1<T>(r_bx, ofx, zp * pfx + 2u * sizeof(T));
+        C.by = bload2<T>(r_by, oc, zp * pfy);
+        C.byu = bload2<T>(r_by, oc, zp * pfy + rowb);
+        C.bzh = bload2<T>(r_bz, oc, (unsigned)min(max(zz + 1, 0), d.nz) * psz);
+    };
+
+    T v[kResLoads];
+    load_plane(z0 - 1, v);
+    store_plane(z0 - 1, v);
+    load_plane(z0, v);
+    store_plane(z0, v);
+    load_plane(z0 + 1, v);
+    Coef C, Cn;
+    load_coef(z0, C);
+    T2 bzl = bload2<T>(r_bz, oc, (unsigned)min(max(z0, 0), d.nz) * psz);
+    double dq = 0.0, dr = 0.0;
+
+    for (int s = z0; s < z1; ++s) {
+        store_plane(s + 1, v);
+        load_plane(s + 2, v);
+        load_coef(s + 1, Cn);
+        lds_barrier();
+        const T* S0 = slot + (s & 3) * kResPlane;
+        const T* Sm = slot + ((s - 1) & 3) * kResPlane;
+        const T* Sp = slot + ((s + 1) & 3) * kResPlane;
+        const int li = (row + 1) * kResEX + (xp - x0) + 2;
+        const T2 c = *reinterpret_cast<const T2*>(S0 + li);
+        const T w = S0[li - 1], ea = S0[li + 2];
+        const T2 sn = *reinterpret_cast<const T2*>(S0 + li - kResEX);
+        const T2 nn = *reinterpret_cast<const T2*>(S0 + li + kResEX);
+        const T2 dn = *reinterpret_cast<const T2*>(Sm + li);
+        const T2 up = *reinterpret_cast<const T2*>(Sp + li);
+        T dg0 = C.bx.x, of0 = C.bx.x * w;
+        dg0 += C.bx.y; of0 += C.bx.y * c.y;
+        dg0 += C.by.x; of0 += C.by.x * sn.x;
+        dg0 += C.byu.x; of0 += C.byu.x * nn.x;
+        dg0 += bzl.x; of0 += bzl.x * dn.x;
+        dg0 += C.bzh.x; of0 += C.bzh.x * up.x;
+        T dg1 = C.bx.y, of1 = C.bx.y * c.x;
+        dg1 += C.bxn; of1 += C.bxn * ea;
+        dg1 += C.by.y; of1 += C.by.y * sn.y;
+        dg1 += C.byu.y; of1 += C.byu.y * nn.y;
+        dg1 += bzl.y; of1 += bzl.y * dn.y;
+        dg1 += C.bzh.y; of1 += C.bzh.y * up.y;
+        if (mine) {
+            T2 qq;
+            qq.x = (of0 - dg0 * c.x) * inv_h2;
+            qq.y = (of1 - dg1 * c.y) * inv_h2;
+            const long cell = (long)s * d.nx * d.ny + (long)y * d.nx + xp;
+            *reinterpret_cast<T2*>(dout + cell) = c;
+            *reinterpret_cast<T2*>(q + cell) = qq;
+            dq += c.x * qq.x + c.y * qq.y;
+            dr += c.x * C.r.x + c.y * C.r.y;
+        }
+        bzl = C.bzh;
+        C = Cn;
+    }
+    const double t0 = block_sum_n<kResNT>(dq, ws);
+    __syncthreads();
+    const double t1 = block_sum_n<kResNT>(dr, ws);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = t0;
+        partials[gridDim.x + blockIdx.x] = t1;
+    }
 }
 
 }  // namespace mgp

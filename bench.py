@@ -44,7 +44,7 @@ KERNEL_SYMBOLS = {
     ("prolong_correct", "mixed"): "mgp::k_prolong_tiled<float>",
     ("prolong_correct", "fp64"): "mgp::k_prolong_tiled<double>",
     ("outer_update", "mixed"): "mgp::k_resid<double, 2>",
-    ("residual_norm", "fp64"): "mgp::k_resid<double, 0>",
+    ("residual_norm", "fp64"): "mgp::k_sweep_fused<double, 16, true>",
 }
 
 # HBM bytes per dispatch of the FP32 two-sweep smoother on the 512^3 film + 32
@@ -129,9 +129,64 @@ def smoother_figures(ksum, cells):
     for name in ("sweep2", "sweep"):
         f = ksum.get(name, {}).get("finest", {})
         if f.get("avg_ms"):
+            cups = SWEEPS_PER_LAUNCH[name] * cells / (f["avg_ms"] * 1e-3)
+            # roofline in cell-updates/s: HBM peak / algorithmic bytes of one sweep per cell
+            bytes_per_update = f["alg_bytes_per_launch"] / (SWEEPS_PER_LAUNCH[name] * cells)
             return {"smoother_kernel": ksum[name]["kernel"], "smoother_gbps_finest": f["achieved_gbps"],
-                    "smoother_cell_updates_per_s": SWEEPS_PER_LAUNCH[name] * cells / (f["avg_ms"] * 1e-3)}
-    return {"smoother_kernel": None, "smoother_gbps_finest": None, "smoother_cell_updates_per_s": None}
+                    "smoother_cell_updates_per_s": cups,
+                    "smoother_cell_update_frac": cups / (HBM_PEAK_GBPS * 1e9 / bytes_per_update)}
+    return {"smoother_kernel": None, "smoother_gbps_finest": None, "smoother_cell_updates_per_s": None,
+            "smoother_cell_update_frac": None}
+
+
+def measure_copy_gbps(stream) -> float:
+    """A STREAM-style device copy (1 GiB read + 1 GiB written, median of 5) on this GPU."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    times = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        y.copy_(x)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del x, y
+    return 2.0 * (1 << 30) / (statistics.median(times) * 1e-3) / 1e9
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "many_drops512_oracle.txt")
+
+
+def sampled_error_vs_oracle(p, n, drops, tol):
+    """Relative RMS error of p on the cells sampled in the stored oracle solution of
+    the 512^3 film + 32 drops workload converged to 1e-12 (None for other workloads)."""
+    import numpy as np
+    import torch
+    if n != 512 or drops != 32 or not os.path.exists(GOLDEN):
+        return None
+    meta, idx, val = {}, [], []
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.startswith("#"):
+                parts = line[1:].split()
+                if len(parts) == 2:
+                    try:
+                        meta[parts[0]] = float(parts[1])
+                    except ValueError:
+                        pass
+                continue
+            a = line.split()
+            idx.append(int(a[0]))
+            val.append(float(a[2]))
+    got = p.reshape(-1)[torch.tensor(idx, device=p.device)].cpu().numpy()
+    rms = meta["tol12_norm2"] / np.sqrt(float(n) ** 3)
+    d = got - np.array(val)
+    return {"sampled_rel_rms": float(np.sqrt(np.mean(d ** 2)) / rms),
+            "sampled_max": float(np.abs(d).max() / rms), "cells": len(idx),
+            "reference": "oracle FP64 V-cycles to rr 1e-12, tests/golden/many_drops512_oracle.txt"}
 
 
 def copy_calibration() -> int:
@@ -230,6 +285,10 @@ def main() -> int:
     mixed_rr = max(s.rel_res for s in solve_stats)
     ksum = kernel_summary(solve_stats + [r[2] for r in recs], "mixed")
     dominant = max(ksum, key=lambda k: ksum[k]["ms_total"]) if ksum else None
+    setup_ms = solve_stats[-1].setup_ms
+    err_vs_oracle = sampled_error_vs_oracle(p, n, args.drops, args.tol)
+    copy_gbps = measure_copy_gbps(stream)
+    log(f"copy {copy_gbps:.0f} GB/s; mixed solve {mixed_ms:.2f} ms")
 
     # plain FP64 solve on the same input, same tolerance
     fp64 = None
@@ -283,10 +342,14 @@ def main() -> int:
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": d["achieved_gbps"] / HBM_PEAK_GBPS if d["achieved_gbps"] else None,
                     "traffic": measured_traffic(d["kernel"], n), "traffic_unit": "HBM bytes per launch",
+                    "copy_gbps": copy_gbps,
+                    "frac_of_copy": d["achieved_gbps"] / copy_gbps if d["achieved_gbps"] else None,
                     "avg_launch_ms": d["avg_ms"],
                     "launches": d["launches"],
                     "alg_bytes_per_launch": d["alg_bytes_per_launch"],
                     "finest": d["finest"]}
+        tr = roofline["traffic"]
+        roofline["traffic_gbps"] = tr / (d["avg_ms"] * 1e-3) / 1e9 if tr else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -309,6 +372,7 @@ def main() -> int:
                    "n": n, "cells": cells, "levels": mixed.num_levels, "precision": "mixed (FP32 V-cycle, FP64 outer)",
                    "pre_post_sweeps": [2, 2], "tol": args.tol},
         "mixed": {"time_to_tol_ms": mixed_ms, "cycles": mixed_cycles, "rel_res_max": mixed_rr,
+                  "setup_ms": setup_ms, "error_vs_oracle": err_vs_oracle,
                   **smoother_figures(ksum, cells),
                   "kernels": ksum},
         "fp64": fp64,

@@ -333,15 +333,15 @@ int convert(mg_ctx* c, const S* x, long n, D* y)
 
 // One V-cycle on level l.  *x holds the iterate (zero_init: treat as 0),
 // *t is its ping-pong partner; on return *x holds the result (the two
-// pointers may have been swapped).
+// pointers may have been swapped).  pre_done pre-sweeps have already run.
 template <typename T>
-int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init)
+int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init, int pre_done = 0)
 {
     Level& L = c->lev[l];
     if (l == c->nlev - 1) return coarse_apply<T>(c, b, *x);
     const int pre = c->opts.pre, post = c->opts.post;
     if (zero_init && pre == 0) TRY(fill<T>(c, *x, L.n, (T)0));
-    TRY(smooth<T>(c, l, b, x, t, 0, pre, zero_init));
+    TRY(smooth<T>(c, l, b, x, t, 0, pre - pre_done, zero_init && pre_done == 0));
     Level& C = c->lev[l + 1];
     LevelBufs<T>& CB = bufs<T>(C);
     TRY(residual_restrict<T>(c, l, b, *x, CB.b));
@@ -351,6 +351,27 @@ int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init)
     TRY(prolong_correct<T>(c, l, cx, *x));
     TRY(smooth<T>(c, l, b, x, t, 1, post, false));
     return MG_OK;
+}
+
+// The first pre-sweep of an FP64 V-cycle on the finest grid (in -> out,
+// order 0) that also leaves ||b - L in||^2 in scal[slot]: the residual norm
+// of the iterate the cycle starts from.  Only for grids the fused sweep
+// kernel covers (sweep_is_fused).
+int sweep_first_norm(mg_ctx* c, const double* b, const double* in, double* out, int slot)
+{
+    Level& L = c->lev[0];
+    LevelBufs<double>& B = L.f64;
+    int blocks = 0;
+    {
+        TimedLaunch tl(c, 0, MG_K_NORM, (double)L.n * sweep_bytes_per_cell<double>(), true);
+        const hipError_t e = launch_fused<double, 16>(B.bx, B.by, B.bz, L.d, L.h * L.h, b, in, out, 0, false,
+                                                      c->stream, c->partials, &blocks);
+        if (e != hipSuccess) {
+            set_err(c, "sweep launch failed: %s", hipGetErrorString(e));
+            return MG_EHIP;
+        }
+    }
+    return reduce_to(c, blocks, slot);
 }
 
 int residual_norm_launch(mg_ctx* c, const double* b, const double* p, double* r_out, int slot)
@@ -572,30 +593,42 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
     if (c->opts.flags & MG_FLAG_FCG) {
         TRY(fcg_loop(c, cur, bnorm, tol, zero_guess, st, &cycles, &rr, &status));
     } else if (!c->mixed) {
-        if (zero_guess) {
-            rr = 1.0;
-        } else {
-            TRY(residual_norm_launch(c, c->b0, cur, nullptr, 2));
-            TRY(fetch_scalars(c, 3));
-            rr = std::sqrt(c->host_scal[2]) / bnorm;
-        }
+        // The residual norm of each iterate is taken by the sweep that starts
+        // the next cycle (it reads exactly the residual's inputs): one pass
+        // fewer per cycle; when the norm says stop, that sweep's output is
+        // dropped.  Grids the fused sweep does not cover use a separate pass.
+        const bool fuse = c->opts.pre > 0 && sweep_is_fused(c->lev[0].d, sizeof(double)) &&
+                          fused_geom<16>(c->lev[0].d).blocks <= kMaxPartials;
+        bool known = zero_guess;  // the rr of the current iterate is known (1 for p = 0)
+        bool swept = false;       // the next cycle's first pre-sweep has run (into `other`)
+        rr = 1.0;
         if (st) st->hist[0] = rr;
-        best = rr;
-        if (!std::isfinite(rr)) status = MG_ENONFINITE;
-        else if (rr <= tol) status = MG_OK;
-        bool first = zero_guess;
-        while (status == MG_ENOCONV && cycles < maxc) {
-            TRY(vcycle<double>(c, 0, &cur, &other, c->b0, first));
-            first = false;
-            ++cycles;
-            TRY(residual_norm_launch(c, c->b0, cur, nullptr, 2));
-            TRY(fetch_scalars(c, 3));
-            rr = std::sqrt(c->host_scal[2]) / bnorm;
-            if (st && cycles < MG_HIST_MAX) st->hist[cycles] = rr;
+        while (true) {
+            if (!known) {
+                if (fuse) {
+                    TRY(sweep_first_norm(c, c->b0, cur, other, 2));
+                    swept = true;
+                } else {
+                    TRY(residual_norm_launch(c, c->b0, cur, nullptr, 2));
+                }
+                TRY(fetch_scalars(c, 3));
+                rr = std::sqrt(c->host_scal[2]) / bnorm;
+                if (st && cycles < MG_HIST_MAX) st->hist[cycles] = rr;
+            }
             if (!std::isfinite(rr)) { status = MG_ENONFINITE; break; }
             if (rr <= tol) { status = MG_OK; break; }
+            if (cycles == 0) best = rr;
             best = std::min(best, rr);
-            if (rr > 1e3 * best) break;
+            if (rr > 1e3 * best || cycles >= maxc) break;
+            if (swept) {
+                std::swap(cur, other);
+                TRY(vcycle<double>(c, 0, &cur, &other, c->b0, false, 1));
+            } else {
+                TRY(vcycle<double>(c, 0, &cur, &other, c->b0, zero_guess && cycles == 0));
+            }
+            swept = false;
+            known = false;
+            ++cycles;
         }
     } else {
         Level& F0 = c->lev[0];

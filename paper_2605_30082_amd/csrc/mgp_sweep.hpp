@@ -55,10 +55,18 @@ struct FusedGeom {
 };
 
 // Launch contract: nx even and >= 64, every array below 2^31 bytes.
-template <typename T, int TY>
+// NORM: also accumulate ||b - L in||^2 of the *input* iterate (its partial per
+// block goes to partials[blockIdx.x]); the input is read before any update,
+// so the sweep that starts a V-cycle yields the residual norm of the previous
+// cycle's result.  Per step s the residual of plane s+1 is formed before the
+// first colour of plane s is updated: plane s and plane s+1 (with its ring)
+// are still the input in LDS, plane s+2 comes from a pair load one step ahead,
+// and plane s+1's coefficients from a register set loaded a step earlier.
+template <typename T, int TY, bool NORM = false>
 __global__ void __launch_bounds__(32 * TY)
 k_sweep_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz, const T* __restrict__ bb,
-        const T* __restrict__ in, T* __restrict__ out, Dims d, T h2, int c0, int zero_in, int zc, int ntx, int nty)
+        const T* __restrict__ in, T* __restrict__ out, Dims d, T h2, int c0, int zero_in, int zc, int ntx, int nty,
+        double* __restrict__ partials = nullptr)
 {
     using G = FusedGeom<TY>;
     using T2 = typename Vec2<T>::type;
@@ -189,9 +197,18 @@ k_sweep_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __res
     load_plane(sbeg, v);
     store_plane(sbeg, v);
     load_plane(sbeg + 1, v);
-    Coef Cp, C, Cn;
+    Coef Cp, C, Cn, Cnn;
     load_coef(sbeg - 1, Cp);
     load_coef(sbeg, C);
+    if constexpr (NORM) load_coef(sbeg + 1, Cn);
+    // NORM: the pair's own input values of plane s+2, one step ahead
+    auto load_pair = [&](int z) -> T2 {
+        const bool zv = !zero_in && z >= 0 && z < d.nz;
+        return bload2<T>(zv ? r_in : r_null, oc, cpl(z) * psz);
+    };
+    T2 p2 = {}, p2n = {};
+    if constexpr (NORM) p2 = load_pair(sbeg + 2);
+    double acc = 0.0;
     T2 zlo_p = bload2<T>(r_bz, oc, (unsigned)min(max(sbeg - 1, 0), d.nz) * psz);  // bz of plane sbeg-1
     Ring R, Rn;
     load_ring(sbeg, R);
@@ -200,12 +217,44 @@ k_sweep_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __res
     for (int s = sbeg; s <= z1; ++s) {
         store_plane(s + 1, v);
         load_plane(s + 2, v);
-        load_coef(s + 1, Cn);
+        if constexpr (NORM) {
+            p2n = load_pair(s + 3);
+            load_coef(s + 2, Cnn);
+        } else {
+            load_coef(s + 1, Cn);
+        }
         load_ring(s + 1, Rn);
         lds_barrier();
         const T* Sm = slot + ((s - 1) & 3) * G::PLANE;
         T* S0 = slot + (s & 3) * G::PLANE;
         const T* Sp = slot + ((s + 1) & 3) * G::PLANE;
+        if constexpr (NORM) {
+            // residual of the input on plane s+1 (planes s, s+1 in LDS, s+2 in p2)
+            if (mine && s + 1 >= z0 && s + 1 < z1) {
+                const int ex = xp - (x0 - 2), ey = y - (y0 - 2);
+                const T cx = Sp[G::idx(ex, ey)], cy = Sp[G::idx(ex + 1, ey)];
+                const T w = Sp[G::idx(ex - 1, ey)], ea = Sp[G::idx(ex + 2, ey)];
+                const T s0 = Sp[G::idx(ex, ey - 1)], s1 = Sp[G::idx(ex + 1, ey - 1)];
+                const T n0 = Sp[G::idx(ex, ey + 1)], n1 = Sp[G::idx(ex + 1, ey + 1)];
+                const T d0 = S0[G::idx(ex, ey)], d1 = S0[G::idx(ex + 1, ey)];
+                const T inv_h2 = (T)1 / h2;
+                T dg0 = Cn.bx.x, of0 = Cn.bx.x * w;
+                dg0 += Cn.bx.y; of0 += Cn.bx.y * cy;
+                dg0 += Cn.by.x; of0 += Cn.by.x * s0;
+                dg0 += Cn.byu.x; of0 += Cn.byu.x * n0;
+                dg0 += C.bzh.x; of0 += C.bzh.x * d0;
+                dg0 += Cn.bzh.x; of0 += Cn.bzh.x * p2.x;
+                T dg1 = Cn.bx.y, of1 = Cn.bx.y * cx;
+                dg1 += Cn.bxn; of1 += Cn.bxn * ea;
+                dg1 += Cn.by.y; of1 += Cn.by.y * s1;
+                dg1 += Cn.byu.y; of1 += Cn.byu.y * n1;
+                dg1 += C.bzh.y; of1 += C.bzh.y * d1;
+                dg1 += Cn.bzh.y; of1 += Cn.bzh.y * p2.y;
+                const T r0 = Cn.b.x - (of0 - dg0 * cx) * inv_h2;
+                const T r1 = Cn.b.y - (of1 - dg1 * cy) * inv_h2;
+                acc += (double)r0 * r0 + (double)r1 * r1;
+            }
+        }
         const bool splane = s >= 0 && s < d.nz;
         const int odd = (xp + y + s + c0) & 1;
         const int xa = xp + odd;
@@ -251,24 +300,61 @@ k_sweep_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __res
         zlo_p = Cp.bzh;
         Cp = C;
         C = Cn;
+        if constexpr (NORM) {
+            Cn = Cnn;
+            p2 = p2n;
+        }
         R = Rn;
+    }
+    if constexpr (NORM) {
+        __shared__ double ws[G::NW];
+        const double v0 = wave_sum(acc);
+        if ((t & 63) == 0) ws[t >> 6] = v0;
+        __syncthreads();
+        if (t == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < G::NW; ++w) tot += ws[w];
+            partials[blockIdx.x] = tot;
+        }
     }
 }
 // Launch of the fused kernel with TY-row tiles; z is split into chunks so that
 // the grid holds about 2048 blocks (at least 16 planes per chunk).
-template <typename T, int TY>
-hipError_t launch_fused(const T* bx, const T* by, const T* bz, Dims d, T h2, const T* b, const T* in, T* out,
-                        int c0, bool zero_in, hipStream_t s)
+struct FusedLaunch {
+    int ntx, nty, zc, blocks;
+};
+
+template <int TY>
+inline FusedLaunch fused_geom(const Dims& d)
 {
-    const int ntx = (d.nx + 63) / 64, nty = (d.ny + TY - 1) / TY;
-    const int tiles = ntx * nty;
+    FusedLaunch g;
+    g.ntx = (d.nx + 63) / 64;
+    g.nty = (d.ny + TY - 1) / TY;
+    const int tiles = g.ntx * g.nty;
     int nzc = (2048 + tiles - 1) / tiles;
     int zc = (d.nz + nzc - 1) / nzc;
     if (zc < 16) zc = 16;
     if (zc >= d.nz) zc = d.nz;
-    nzc = (d.nz + zc - 1) / zc;
-    k_sweep_fused<T, TY><<<tiles * nzc, 32 * TY, 0, s>>>(bx, by, bz, b, in, out, d, h2, c0, zero_in ? 1 : 0, zc,
-                                                          ntx, nty);
+    g.zc = zc;
+    g.blocks = tiles * ((d.nz + zc - 1) / zc);
+    return g;
+}
+
+template <typename T, int TY>
+hipError_t launch_fused(const T* bx, const T* by, const T* bz, Dims d, T h2, const T* b, const T* in, T* out,
+                        int c0, bool zero_in, hipStream_t s, double* norm_partials = nullptr,
+                        int* norm_blocks = nullptr)
+{
+    const FusedLaunch g = fused_geom<TY>(d);
+    const int ntx = g.ntx, nty = g.nty, zc = g.zc, tiles = ntx * nty, nzc = g.blocks / tiles;
+    if (norm_partials) {
+        *norm_blocks = tiles * nzc;
+        k_sweep_fused<T, TY, true><<<tiles * nzc, 32 * TY, 0, s>>>(bx, by, bz, b, in, out, d, h2, c0,
+                                                                    zero_in ? 1 : 0, zc, ntx, nty, norm_partials);
+    } else {
+        k_sweep_fused<T, TY><<<tiles * nzc, 32 * TY, 0, s>>>(bx, by, bz, b, in, out, d, h2, c0, zero_in ? 1 : 0, zc,
+                                                              ntx, nty);
+    }
     return hipGetLastError();
 }
 

@@ -186,3 +186,29 @@ def test_fcg_512(big, precision):
          f"sampled rel vs converged oracle {sampled:.3e}")
     assert st.rel_res <= 1e-10 and rr <= 1.01e-10
     assert sampled < 1e-9
+
+
+def test_largest_arrays_layered_exact():
+    """1024 x 1024 x 256 cells: the FP64 face arrays exceed 2^31 bytes, so the FP64
+    finest level runs the simple kernels (and the mixed outer update its simple form)
+    while the FP32 V-cycle stays tiled.  Checked against the exact z-layered solution."""
+    dims = (1024, 1024, 256)
+    h = 1.0 / 1024
+    wl = W.layered_film_workload(dims, height=0.1)
+    f = wl.f_film[:, 0, 0]
+    rho = W.RHO_FILM * f + W.RHO_GAS * (1.0 - f)
+    g = np.random.default_rng(23).standard_normal(dims[2])
+    rhs, p_ref = refs.layered_solve(dims, h, rho, 3, 1, g)
+    gb = S.faces_from_vof(T(wl.f_drop), T(wl.f_film), wl.rho_drop, wl.rho_film, wl.rho_gas)
+    del wl
+    assert gb[0].numel() * 8 > 2 ** 31
+    grhs = T(rhs)
+    del rhs
+    for precision in ("mixed", "fp64"):
+        s = S.Solver(*gb, h, precision=precision, zero_guess=True)
+        p, st = s.solve(grhs, 1e-10)
+        err = rel_l2(N(p), p_ref)
+        note(f"1024x1024x256 {precision}: cycles {st.cycles} rr {st.rel_res:.3e} rel err vs exact {err:.3e}")
+        assert st.rel_res <= 1e-10 and err < 1e-9
+        del p
+        s.close()

@@ -84,7 +84,7 @@ __global__ void k_fcg_update(double* __restrict__ x, double* __restrict__ r, con
 }
 
 // The direction update and q = L d in one tiled pass (the tiling of k_resid:
-// 64 x 8 tiles marching in z, one LDS plane per step): while a plane of d is
+// 64 x 32 tiles marching in z, one LDS plane per step): while a plane of d is
 // staged into LDS it is formed as z - gamma d_prev (gamma = scal[zq_slot] /
 // dq_prev; first: d = z), with its 1-cell ring recomputed rather than
 // exchanged.  Each thread writes d and q for its pair and accumulates (d, q)

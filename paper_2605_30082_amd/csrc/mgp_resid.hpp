@@ -3,7 +3,8 @@
 //   RES_RESTRICT  coarse rhs = mean of the 8 children of r (multigrid restriction)
 //   RES_OUTER     mixed-precision outer step: q = p + e (e FP32), r = b - L q,
 //                 p_out = q, r32 = (float) r, partial sums of ||r||^2
-// A block owns a 64 x 8 tile of (x, y) and a chunk of z.  Each thread owns a
+// A block owns a 64 x 32 tile of (x, y) and a chunk of z (tall tiles: the 1-cell
+// ring of x re-read by neighbouring tiles is 1/16 of a tile row count, not 1/4).  Each thread owns a
 // pair of x-adjacent cells of one row.  Per z-step s it writes plane s+1 of x
 // (tile plus a 1-cell ring) into one of four LDS slots, issues the loads of
 // the next plane, and after a single barrier forms the residual of its pair on
@@ -18,7 +19,7 @@ namespace mgp {
 
 enum { RES_NORM = 0, RES_RESTRICT = 1, RES_OUTER = 2 };
 
-constexpr int kResTY = 8;                   // tile rows
+constexpr int kResTY = 32;                  // tile rows
 constexpr int kResNT = 32 * kResTY;         // threads per block
 constexpr int kResEX = 68;                  // LDS row: x0-2 .. x0+65 (pairs stay 2-aligned)
 constexpr int kResEY = kResTY + 2;          // LDS rows: y0-1 .. y0+TY

@@ -2,8 +2,8 @@
 //
 // P is cell-centred trilinear interpolation: per axis a fine cell takes 3/4 of
 // its parent and 1/4 of the parent's neighbour on its side, the parent itself
-// standing in for a neighbour beyond a wall.  A block owns a 64 x 8 fine tile
-// (a 32 x 4 coarse tile) and a chunk of coarse planes.  Per coarse plane K it
+// standing in for a neighbour beyond a wall.  A block owns a 64 x 32 fine tile
+// (a 32 x 16 coarse tile) and a chunk of coarse planes.  Per coarse plane K it
 // stages coarse plane K+1 (tile plus a 1-cell ring, read at clamped
 // coordinates so that the wall rule needs no branch) into one of four LDS
 // slots, then each thread updates its fine cell pair in fine planes 2K and 2K+1
@@ -14,10 +14,10 @@
 
 namespace mgp {
 
-constexpr int kProTY = 8;                 // fine rows per tile
+constexpr int kProTY = 32;                // fine rows per tile
 constexpr int kProNT = 32 * kProTY;       // threads: one fine pair each
 constexpr int kProCX = 34;                // coarse LDS row: X0-1 .. X0+32
-constexpr int kProCY = kProTY / 2 + 2;    // coarse LDS rows: Y0-1 .. Y0+4
+constexpr int kProCY = kProTY / 2 + 2;    // coarse LDS rows: Y0-1 .. Y0+16
 constexpr int kProPlane = kProCX * kProCY;
 constexpr int kProLoads = (kProPlane + kProNT - 1) / kProNT;
 

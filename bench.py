@@ -59,8 +59,8 @@ TRAFFIC = {
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp"],
     "sha256": "9220d93dd2b7cf43a004c1012c1b169df9bcd363ad3aef47269dec7e73793687",
-    "fetch_kib": 404067.31640625,
-    "write_kib": 149763.85166015624,
+    "fetch_kib": 402975.7794921875,
+    "write_kib": 149763.7951171875,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

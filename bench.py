@@ -8,12 +8,14 @@ seeded uniform [-1, 1] face velocity; homogeneous Neumann walls; tolerance 1e-10
 on the relative residual.
 
 One step = the whole hot path on that input, all on the GPU:
-  update   new face coefficients, coarse levels and coarse inverse (no allocation)
+  update   new coefficients (the cell density; --coefficients faces: the three
+           face arrays), coarse levels and coarse inverse (no allocation)
   solve    FP32 V-cycles inside the FP64 defect-correction loop, p = 0 start
   adjoint  same solve for L lambda = w - mean(w), w ~ N(0,1)
   grad     fused face-gradient kernel (lambda_R - lambda_L)(p_R - p_L)/h^2
 The headline value is the median time-to-1e-10 of the solve inside those steps.
-The plain-FP64 solve on the same input is timed after the steps for comparison.
+The same mixed solve from the face arrays (identical result), the plain-FP64 solve
+and the flexible-CG solves on the same input are timed after the steps for comparison.
 
 Prints ONE JSON line.  --gpus above 1 is refused: the solver is single-GPU.
 """
@@ -36,16 +38,23 @@ KERNEL_NAMES = ["sweep", "residual_restrict", "prolong_correct", "outer_update",
 SWEEPS_PER_LAUNCH = {"sweep": 1, "sweep2": 2}
 # kernel symbol timed for each class (one per class and precision), as rocprofv3 names it
 KERNEL_SYMBOLS = {
-    ("sweep", "mixed"): "mgp::k_sweep_fused<float, 8>",
-    ("sweep", "fp64"): "mgp::k_sweep_fused<double, 16>",
+    ("sweep", "mixed"): "mgp::k_sweep_fused<float, 8, false>",
+    ("sweep", "fp64"): "mgp::k_sweep_fused<double, 16, false>",
     ("sweep2", "mixed"): "mgp::k_sweep2_fused<float, 16>",
-    ("residual_restrict", "mixed"): "mgp::k_resid<float, 1>",
-    ("residual_restrict", "fp64"): "mgp::k_resid<double, 1>",
+    ("residual_restrict", "mixed"): "mgp::k_resid<float, 1, false>",
+    ("residual_restrict", "fp64"): "mgp::k_resid<double, 1, {rho}>",
     ("prolong_correct", "mixed"): "mgp::k_prolong_tiled<float>",
     ("prolong_correct", "fp64"): "mgp::k_prolong_tiled<double>",
-    ("outer_update", "mixed"): "mgp::k_resid<double, 2>",
+    ("outer_update", "mixed"): "mgp::k_resid<double, 2, {rho}>",
     ("residual_norm", "fp64"): "mgp::k_sweep_fused<double, 16, true>",
 }
+
+
+def kernel_symbol(name, precision, coefficients):
+    """rocprofv3's name of the kernel timed for a class; finest-grid FP64 residual
+    passes have a density-fed instance (coefficients formed from rho)."""
+    sym = KERNEL_SYMBOLS.get((name, precision))
+    return sym.format(rho="true" if coefficients == "density" else "false") if sym else None
 
 # HBM bytes per dispatch of the FP32 two-sweep smoother on the 512^3 film + 32
 # drops workload (average over all levels, the unit of the roofline figure), from
@@ -96,12 +105,15 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solves")
     ap.add_argument("--no-fcg", action="store_true", help="skip the flexible-CG variant solves")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: all available)")
+    ap.add_argument("--coefficients", choices=["density", "faces"], default="density",
+                    help="hand the solver the cell density (coefficients formed on the fly in the finest "
+                         "FP64 residual passes) or the three face arrays")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (scales PMC byte counters)")
     return ap.parse_args()
 
 
-def kernel_summary(stats_list, precision):
+def kernel_summary(stats_list, precision, coefficients):
     """Per kernel class: HIP-event timings summed over several solves, for all
     launches of the class's kernel (every level) and for the finest grid alone."""
     out = {}
@@ -113,7 +125,7 @@ def kernel_summary(stats_list, precision):
         n0 = sum(s.kernel_launches_finest[k] for s in stats_list)
         by0 = sum(s.kernel_bytes_finest[k] for s in stats_list)
         if n:
-            out[name] = {"kernel": KERNEL_SYMBOLS.get((name, precision)),
+            out[name] = {"kernel": kernel_symbol(name, precision, coefficients),
                          "ms_total": ms, "launches": n, "avg_ms": ms / n, "alg_bytes_per_launch": by / n,
                          "achieved_gbps": by / (ms * 1e-3) / 1e9 if ms > 0 else None,
                          "finest": {"launches": n0, "avg_ms": ms0 / n0 if n0 else None,
@@ -235,21 +247,36 @@ def main() -> int:
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
     f_drop, f_film = T(wl.f_drop), T(wl.f_film)
+    coef = args.coefficients
     beta = S.faces_from_vof(f_drop, f_film, wl.rho_drop, wl.rho_film, wl.rho_gas)
+    if coef == "density":
+        rho = S.density_from_vof(f_drop, f_film, wl.rho_drop, wl.rho_film, wl.rho_gas)
+
+        def make(**kw):
+            return S.Solver.from_density(rho, wl.h, **kw)
+
+        def update(s):
+            s.update_density(rho)
+    else:
+        def make(**kw):
+            return S.Solver(*beta, wl.h, **kw)
+
+        def update(s):
+            s.update(*beta)
     rhs = S.divergence(T(wl.u), T(wl.v), T(wl.w), wl.h, wl.dt)
     w = T(w_np)
     torch.cuda.synchronize()
-    log("inputs resident in HBM")
+    log(f"inputs resident in HBM (coefficients: {coef})")
 
     stream = torch.cuda.current_stream()
-    mixed = S.Solver(*beta, wl.h, precision="mixed", zero_guess=True, timing=True)
+    mixed = make(precision="mixed", zero_guess=True, timing=True)
     p = torch.zeros_like(rhs)
     lam = torch.zeros_like(rhs)
 
     def step(record):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         ev[0].record(stream)
-        mixed.update(*beta)
+        update(mixed)
         ev[1].record(stream)
         _, st = mixed.solve(rhs, args.tol, p=p)
         ev[2].record(stream)
@@ -283,17 +310,36 @@ def main() -> int:
     mixed_ms = statistics.median(phases["solve"])
     mixed_cycles = solve_stats[-1].cycles
     mixed_rr = max(s.rel_res for s in solve_stats)
-    ksum = kernel_summary(solve_stats + [r[2] for r in recs], "mixed")
+    ksum = kernel_summary(solve_stats + [r[2] for r in recs], "mixed", coef)
     dominant = max(ksum, key=lambda k: ksum[k]["ms_total"]) if ksum else None
     setup_ms = solve_stats[-1].setup_ms
     err_vs_oracle = sampled_error_vs_oracle(p, n, args.drops, args.tol)
     copy_gbps = measure_copy_gbps(stream)
     log(f"copy {copy_gbps:.0f} GB/s; mixed solve {mixed_ms:.2f} ms")
 
+    # the same mixed solve from the three face arrays (identical result, more bytes)
+    mixed_faces = None
+    if coef == "density":
+        with S.Solver(*beta, wl.h, precision="mixed", zero_guess=True, timing=True) as sfc:
+            pfc = torch.zeros_like(rhs)
+            sfc.solve(rhs, args.tol, p=pfc)
+            times = []
+            for _ in range(max(1, args.steps)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                _, stc = sfc.solve(rhs, args.tol, p=pfc)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            mixed_faces = {"time_to_tol_ms": statistics.median(times), "cycles": stc.cycles,
+                           "identical_solution": bool(torch.equal(pfc, p))}
+            del pfc
+        log(f"mixed solve from face arrays {mixed_faces['time_to_tol_ms']:.2f} ms")
+
     # plain FP64 solve on the same input, same tolerance
     fp64 = None
     if not args.no_fp64:
-        with S.Solver(*beta, wl.h, precision="fp64", zero_guess=True, timing=True) as s64:
+        with make(precision="fp64", zero_guess=True, timing=True) as s64:
             p64 = torch.zeros_like(rhs)
             s64.solve(rhs, args.tol, p=p64)
             times, st64 = [], []
@@ -305,7 +351,7 @@ def main() -> int:
                 torch.cuda.synchronize()
                 times.append(e0.elapsed_time(e1))
                 st64.append(st)
-            ks64 = kernel_summary(st64, "fp64")
+            ks64 = kernel_summary(st64, "fp64", coef)
             fp64 = {"time_to_tol_ms": statistics.median(times), "cycles": st64[-1].cycles,
                     "rel_res": st64[-1].rel_res, "kernels": ks64, **smoother_figures(ks64, cells)}
             diff = float(torch.linalg.vector_norm(p - p64) / torch.linalg.vector_norm(p64))
@@ -319,7 +365,7 @@ def main() -> int:
     if not args.no_fcg:
         fcg = {}
         for prec in ("mixed", "fp64"):
-            with S.Solver(*beta, wl.h, precision=prec, zero_guess=True, method="fcg") as sf:
+            with make(precision=prec, zero_guess=True, method="fcg") as sf:
                 pf = torch.zeros_like(rhs)
                 sf.solve(rhs, args.tol, p=pf)
                 times, stf = [], None
@@ -370,11 +416,12 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"film + {args.drops} drops, {n}^3 cells, rho 960/1000/1.2, Neumann, tol {args.tol:g}",
                    "n": n, "cells": cells, "levels": mixed.num_levels, "precision": "mixed (FP32 V-cycle, FP64 outer)",
-                   "pre_post_sweeps": [2, 2], "tol": args.tol},
+                   "pre_post_sweeps": [2, 2], "tol": args.tol, "coefficients": coef},
         "mixed": {"time_to_tol_ms": mixed_ms, "cycles": mixed_cycles, "rel_res_max": mixed_rr,
                   "setup_ms": setup_ms, "error_vs_oracle": err_vs_oracle,
                   **smoother_figures(ksum, cells),
                   "kernels": ksum},
+        "mixed_from_faces": mixed_faces,
         "fp64": fp64,
         "fcg": fcg,
         "phases_ms": {k: statistics.median(v) for k, v in phases.items()},

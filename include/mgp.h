@@ -153,6 +153,30 @@ int mg_setup(mg_ctx **out, const double *beta_x, const double *beta_y, const dou
              const int dims[3], double h, int bc, const mg_opts *opts, void *hip_stream);
 
 /*
+ * mg_setup_density -- mg_setup for coefficients defined by a cell density:
+ * beta_f = 2/(rho_L + rho_R) on interior faces and 0 on walls, the face value
+ * of the variable density of the projection equation (Sec. 2, with the
+ * density of eq. "property_calculation" from mg_density_from_vof).
+ *   rho  device [nz][ny][nx]; every entry finite and > 0, else MG_EINVAL.
+ *        Copied into the context (one more cell array of device memory).
+ * Other arguments, the level hierarchy and the results are those of mg_setup
+ * given the faces mg_faces_from_density(rho) writes, bit for bit.  The
+ * difference is bandwidth: the finest-grid FP64 residual passes (the
+ * mixed-precision outer update, the FP64 restriction and residual norm) form
+ * each coefficient from rho as they go, reading 8 bytes per cell where the
+ * three face arrays take 24.
+ */
+int mg_setup_density(mg_ctx **out, const double *rho, const int dims[3], double h, int bc,
+                     const mg_opts *opts, void *hip_stream);
+
+/*
+ * mg_update_density -- new cell density for a context made by mg_setup_density
+ * (same rules; MG_EINVAL for any other context).  mg_update on such a context
+ * switches it to the face arrays given, and mg_update_density back.
+ */
+int mg_update_density(mg_ctx *c, const double *rho);
+
+/*
  * mg_update -- replace the face coefficients of an existing context (same dims,
  * layouts and rules as mg_setup) and rebuild the coarse levels and the coarse
  * inverse, without allocating: the per-time-step call of a flow solver whose
@@ -216,6 +240,23 @@ const char *mg_last_error(const mg_ctx *c);
 int mg_faces_from_vof(const double *f_drop, const double *f_film, const int dims[3],
                       double rho_drop, double rho_film, double rho_gas,
                       double *beta_x, double *beta_y, double *beta_z, void *hip_stream);
+
+/*
+ * mg_density_from_vof -- rho = rho_drop f_drop + rho_film f_film
+ * + rho_gas max(0, 1 - f_drop - f_film) per cell (Sec. 2, eq.
+ * "property_calculation"), each product rounded as written (no fused
+ * multiply-add), so that mg_faces_from_density of the result equals
+ * mg_faces_from_vof bit for bit.  f_drop, f_film, rho: device cell arrays.
+ */
+int mg_density_from_vof(const double *f_drop, const double *f_film, const int dims[3],
+                        double rho_drop, double rho_film, double rho_gas, double *rho, void *hip_stream);
+
+/*
+ * mg_faces_from_density -- beta_f = 2/(rho_L + rho_R) on interior faces, 0 on
+ * walls (public face layouts, device), from a device cell density.
+ */
+int mg_faces_from_density(const double *rho, const int dims[3], double *beta_x, double *beta_y,
+                          double *beta_z, void *hip_stream);
 
 /*
  * mg_divergence -- b = div_h(u, v, w) / dt for MAC face velocities

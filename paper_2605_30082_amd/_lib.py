@@ -52,6 +52,8 @@ _DIMS = ctypes.POINTER(ctypes.c_int)
 SIGNATURES = {
     "mg_setup": (_I, [ctypes.POINTER(_CTX), _D, _D, _D, _DIMS, _F, _I, ctypes.POINTER(MgOpts), ctypes.c_void_p]),
     "mg_update": (_I, [_CTX, _D, _D, _D]),
+    "mg_setup_density": (_I, [ctypes.POINTER(_CTX), _D, _DIMS, _F, _I, ctypes.POINTER(MgOpts), ctypes.c_void_p]),
+    "mg_update_density": (_I, [_CTX, _D]),
     "mg_solve": (_I, [_CTX, _D, _D, _F, ctypes.POINTER(MgStats)]),
     "mg_solve_adjoint": (_I, [_CTX, _D, _D, _F, ctypes.POINTER(MgStats)]),
     "mg_face_grad": (_I, [_CTX, _D, _D, _D, _D, _D]),
@@ -60,6 +62,8 @@ SIGNATURES = {
     "mg_last_error": (ctypes.c_char_p, [_CTX]),
     "mg_faces_from_vof": (_I, [_D, _D, _DIMS, _F, _F, _F, _D, _D, _D, ctypes.c_void_p]),
     "mg_divergence": (_I, [_D, _D, _D, _DIMS, _F, _F, _D, ctypes.c_void_p]),
+    "mg_density_from_vof": (_I, [_D, _D, _DIMS, _F, _F, _F, _D, ctypes.c_void_p]),
+    "mg_faces_from_density": (_I, [_D, _DIMS, _D, _D, _D, ctypes.c_void_p]),
     "mg_vof_grad": (_I, [_D, _D, _DIMS, _F, _F, _F, _D, _D, _D, _D, _D, ctypes.c_void_p]),
     "mg_velocity_correct": (_I, [_D, _D, _D, _D, _DIMS, _F, _F, _D, _D, _D, ctypes.c_void_p]),
     "mg_plan_levels": (_I, [_DIMS, _I]),

@@ -59,6 +59,8 @@ struct mg_ctx {
     double* fd_buf[2] = {nullptr, nullptr};
     double* fq = nullptr;
     double* partials = nullptr;  // kReduceBlocks
+    double* rho = nullptr;       // cell density (contexts made by mg_setup_density)
+    bool use_rho = false;        // finest FP64 passes form coefficients from rho
     double* scal = nullptr;      // device scalars
     double* host_scal = nullptr; // pinned host mirror
     void* arena = nullptr;
@@ -269,9 +271,19 @@ int residual_restrict(mg_ctx* c, int l, const T* b, const T* x, T* bc)
     Level& C = c->lev[l + 1];
     LevelBufs<T>& B = bufs<T>(L);
     const bool tiled = res_tiled_ok(L.d, sizeof(T));
-    TimedLaunch tl(c, l, MG_K_RESTRICT, (double)L.n * (5.0 + 1.0 / 8.0) * sizeof(T), tiled);
+    const double arrays = (sizeof(T) == 8 && l == 0 && c->use_rho) ? 3.0 : 5.0;  // x, b, faces or rho
+    TimedLaunch tl(c, l, MG_K_RESTRICT, (double)L.n * (arrays + 1.0 / 8.0) * sizeof(T), tiled);
     if (tiled) {
         const ResGeom g = res_geom(L.d);
+        if constexpr (sizeof(T) == 8) {
+            if (l == 0 && c->use_rho) {
+                k_resid<T, RES_RESTRICT, true><<<g.blocks, kResNT, 0, c->stream>>>(
+                    B.bx, B.by, B.bz, b, x, nullptr, L.d, (T)(1.0 / (L.h * L.h)), g.zc, g.ntx, g.nty, nullptr,
+                    nullptr, bc, nullptr, c->rho);
+                CHECK_LAUNCH(c);
+                return MG_OK;
+            }
+        }
         k_resid<T, RES_RESTRICT><<<g.blocks, kResNT, 0, c->stream>>>(B.bx, B.by, B.bz, b, x, nullptr, L.d,
                                                                       (T)(1.0 / (L.h * L.h)), g.zc, g.ntx, g.nty,
                                                                       nullptr, nullptr, bc, nullptr);
@@ -378,12 +390,18 @@ int residual_norm_launch(mg_ctx* c, const double* b, const double* p, double* r_
 {
     Level& L = c->lev[0];
     const bool tiled = !r_out && res_tiled_ok(L.d, sizeof(double));
-    TimedLaunch tl(c, 0, MG_K_NORM, (double)L.n * 5.0 * sizeof(double), tiled);
+    TimedLaunch tl(c, 0, MG_K_NORM, (double)L.n * (c->use_rho ? 3.0 : 5.0) * sizeof(double), tiled);
     if (tiled) {
         const ResGeom g = res_geom(L.d);
-        k_resid<double, RES_NORM><<<g.blocks, kResNT, 0, c->stream>>>(L.f64.bx, L.f64.by, L.f64.bz, b, p, nullptr,
-                                                                       L.d, 1.0 / (L.h * L.h), g.zc, g.ntx, g.nty,
-                                                                       nullptr, nullptr, nullptr, c->partials);
+        if (c->use_rho)
+            k_resid<double, RES_NORM, true><<<g.blocks, kResNT, 0, c->stream>>>(
+                L.f64.bx, L.f64.by, L.f64.bz, b, p, nullptr, L.d, 1.0 / (L.h * L.h), g.zc, g.ntx, g.nty, nullptr,
+                nullptr, nullptr, c->partials, c->rho);
+        else
+            k_resid<double, RES_NORM><<<g.blocks, kResNT, 0, c->stream>>>(L.f64.bx, L.f64.by, L.f64.bz, b, p,
+                                                                           nullptr, L.d, 1.0 / (L.h * L.h), g.zc,
+                                                                           g.ntx, g.nty, nullptr, nullptr, nullptr,
+                                                                           c->partials);
         CHECK_LAUNCH(c);
         return reduce_to(c, g.blocks, slot);
     }
@@ -398,14 +416,20 @@ int residual_norm_launch(mg_ctx* c, const double* b, const double* p, double* r_
 int outer_update(mg_ctx* c, const double* p_in, const float* e, double* p_out, float* r32, int slot)
 {
     Level& F = c->lev[0];
-    const double bytes = (double)F.n * (5 * 8 + (e ? 4 : 0) + 8 + 4);
+    const double bytes = (double)F.n * ((c->use_rho ? 3 : 5) * 8 + (e ? 4 : 0) + 8 + 4);
     const bool tiled = res_tiled_ok(F.d, sizeof(double));
     TimedLaunch tl(c, 0, MG_K_OUTER, bytes, tiled);
     if (tiled) {
         const ResGeom g = res_geom(F.d);
-        k_resid<double, RES_OUTER><<<g.blocks, kResNT, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, c->b0, p_in,
-                                                                        e, F.d, 1.0 / (F.h * F.h), g.zc, g.ntx,
-                                                                        g.nty, p_out, r32, nullptr, c->partials);
+        if (c->use_rho)
+            k_resid<double, RES_OUTER, true><<<g.blocks, kResNT, 0, c->stream>>>(
+                F.f64.bx, F.f64.by, F.f64.bz, c->b0, p_in, e, F.d, 1.0 / (F.h * F.h), g.zc, g.ntx, g.nty, p_out, r32,
+                nullptr, c->partials, c->rho);
+        else
+            k_resid<double, RES_OUTER><<<g.blocks, kResNT, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, c->b0,
+                                                                            p_in, e, F.d, 1.0 / (F.h * F.h), g.zc,
+                                                                            g.ntx, g.nty, p_out, r32, nullptr,
+                                                                            c->partials);
         CHECK_LAUNCH(c);
         return reduce_to(c, g.blocks, slot);
     }
@@ -728,6 +752,7 @@ void carve(mg_ctx* c, Arena& a)
     c->work = a.take<double>(std::max<long>(m * 2 * m, n0));
     c->partials = a.take<double>(kMaxPartials);
     c->scal = a.take<double>(16);
+    if (c->use_rho) c->rho = a.take<double>(n0);
     if (c->opts.flags & MG_FLAG_FCG) {
         c->fr = a.take<double>(n0);
         c->fd_buf[0] = a.take<double>(n0);
@@ -754,11 +779,21 @@ void carve(mg_ctx* c, Arena& a)
     }
 }
 
-int setup_impl(mg_ctx* c, const double* pbx, const double* pby, const double* pbz)
+// Finest-level coefficients from the caller's faces, or (rho != NULL) from a
+// cell density copied into the context; then the coarse levels, the FP32
+// copies and the coarsest inverse.
+int setup_impl(mg_ctx* c, const double* pbx, const double* pby, const double* pbz, const double* rho = nullptr)
 {
     Level& F = c->lev[0];
-    k_import_faces<<<kReduceBlocks, kBlock, 0, c->stream>>>(pbx, pby, pbz, F.d, F.f64.bx, F.f64.by, F.f64.bz,
-                                                            c->partials);
+    if (rho) {
+        HIP_TRY(c, hipMemcpyAsync(c->rho, rho, sizeof(double) * F.n, hipMemcpyDeviceToDevice, c->stream));
+        k_faces_from_density<true><<<kReduceBlocks, kBlock, 0, c->stream>>>(c->rho, F.d, F.f64.bx, F.f64.by,
+                                                                            F.f64.bz, c->partials);
+    } else {
+        k_import_faces<<<kReduceBlocks, kBlock, 0, c->stream>>>(pbx, pby, pbz, F.d, F.f64.bx, F.f64.by, F.f64.bz,
+                                                                c->partials);
+    }
+    c->use_rho = rho != nullptr;
     CHECK_LAUNCH(c);
     TRY(reduce_to(c, kReduceBlocks, 4));
     for (int l = 1; l < c->nlev; ++l) {
@@ -784,7 +819,9 @@ int setup_impl(mg_ctx* c, const double* pbx, const double* pby, const double* pb
     CHECK_LAUNCH(c);
     TRY(fetch_scalars(c, 6));
     if (c->host_scal[4] != 0.0) {
-        set_err(c, "%.0f interior face coefficient(s) are not finite and > 0", c->host_scal[4]);
+        set_err(c, rho ? "%.0f interior face(s) with a density or coefficient that is not finite and > 0"
+                       : "%.0f interior face coefficient(s) are not finite and > 0",
+                c->host_scal[4]);
         return MG_EINVAL;
     }
     if (c->host_scal[5] != 0.0) {
@@ -827,8 +864,13 @@ int mg_plan_levels(const int dims[3], int coarse_max)
     return plan(dims[0], dims[1], dims[2], coarse_max, nullptr);
 }
 
-int mg_setup(mg_ctx** out, const double* beta_x, const double* beta_y, const double* beta_z, const int dims[3],
-             double h, int bc, const mg_opts* opts, void* hip_stream)
+}  // extern "C"
+
+namespace {
+
+// mg_setup (rho == NULL) and mg_setup_density (faces NULL)
+int setup_ctx(mg_ctx** out, const double* beta_x, const double* beta_y, const double* beta_z, const double* rho,
+              const int dims[3], double h, int bc, const mg_opts* opts, void* hip_stream)
 {
     if (!out) return MG_EINVAL;
     *out = nullptr;
@@ -844,10 +886,11 @@ int mg_setup(mg_ctx** out, const double* beta_x, const double* beta_y, const dou
         free_ctx(c);
         return status;
     };
-    if (!beta_x || !beta_y || !beta_z || !dims) {
+    if ((!rho && (!beta_x || !beta_y || !beta_z)) || !dims) {
         set_err(c, "NULL argument");
         return fail(MG_EINVAL);
     }
+    c->use_rho = rho != nullptr;  // carve() then reserves the density copy
     if (bc != MG_BC_NEUMANN) {
         set_err(c, "only MG_BC_NEUMANN is supported");
         return fail(MG_EINVAL);
@@ -912,11 +955,46 @@ int mg_setup(mg_ctx** out, const double* beta_x, const double* beta_y, const dou
                 return fail(MG_EHIP);
             }
     }
-    const int st = setup_impl(c, beta_x, beta_y, beta_z);
+    const int st = setup_impl(c, beta_x, beta_y, beta_z, rho);
     if (st != MG_OK) return fail(st);
     c->valid = true;
     c->setup_ms = now_ms() - t0;
     *out = c;
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_setup(mg_ctx** out, const double* beta_x, const double* beta_y, const double* beta_z, const int dims[3],
+             double h, int bc, const mg_opts* opts, void* hip_stream)
+{
+    return setup_ctx(out, beta_x, beta_y, beta_z, nullptr, dims, h, bc, opts, hip_stream);
+}
+
+int mg_setup_density(mg_ctx** out, const double* rho, const int dims[3], double h, int bc, const mg_opts* opts,
+                     void* hip_stream)
+{
+    return setup_ctx(out, nullptr, nullptr, nullptr, rho, dims, h, bc, opts, hip_stream);
+}
+
+int mg_update_density(mg_ctx* c, const double* rho)
+{
+    TRY(check_ctx(c));
+    if (!rho) {
+        set_err(c, "NULL argument");
+        return MG_EINVAL;
+    }
+    if (!c->rho) {
+        set_err(c, "the context was not set up from a density (mg_setup_density)");
+        return MG_EINVAL;
+    }
+    const double t0 = now_ms();
+    c->valid = false;
+    TRY(setup_impl(c, nullptr, nullptr, nullptr, rho));
+    c->valid = true;
+    c->setup_ms = now_ms() - t0;
     return MG_OK;
 }
 
@@ -1003,6 +1081,31 @@ int mg_faces_from_vof(const double* f_drop, const double* f_film, const int dims
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     k_faces_from_vof<<<grid_for(total), kBlock, 0, s>>>(f_drop, f_film, d, rho_drop, rho_film, rho_gas, beta_x,
                                                         beta_y, beta_z);
+    return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
+}
+
+int mg_density_from_vof(const double* f_drop, const double* f_film, const int dims[3], double rho_drop,
+                        double rho_film, double rho_gas, double* rho, void* hip_stream)
+{
+    if (!f_drop || !f_film || !dims || !rho) return MG_EINVAL;
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return MG_EINVAL;
+    if (!(rho_drop > 0) || !(rho_film > 0) || !(rho_gas > 0)) return MG_EINVAL;
+    const long n = (long)dims[0] * dims[1] * dims[2];
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    k_density_from_vof<<<grid_for(n), kBlock, 0, s>>>(f_drop, f_film, n, rho_drop, rho_film, rho_gas, rho);
+    return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
+}
+
+int mg_faces_from_density(const double* rho, const int dims[3], double* beta_x, double* beta_y, double* beta_z,
+                          void* hip_stream)
+{
+    if (!rho || !dims || !beta_x || !beta_y || !beta_z) return MG_EINVAL;
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return MG_EINVAL;
+    const Dims d{dims[0], dims[1], dims[2]};
+    const long total = (long)d.nz * d.ny * (d.nx + 1) + (long)d.nz * (d.ny + 1) * d.nx +
+                       (long)(d.nz + 1) * d.ny * d.nx;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    k_faces_from_density<false><<<grid_for(total), kBlock, 0, s>>>(rho, d, beta_x, beta_y, beta_z, nullptr);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 

@@ -627,6 +627,65 @@ __global__ void k_faces_from_vof(const double* __restrict__ fd, const double* __
     }
 }
 
+// rho = sum_i rho_i f_i per cell
+__global__ void k_density_from_vof(const double* __restrict__ fd, const double* __restrict__ ff, long n,
+                                   double rd, double rf, double rg, double* __restrict__ rho)
+{
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock)
+        rho[i] = cell_density(fd[i], ff[i], rd, rf, rg);
+}
+
+// Face coefficients 2/(rho_L + rho_R) from a cell density, 0 on walls.  PAD
+// writes the internal layouts (x rows nx+2 long, padding 0) and a partial count
+// of interior faces whose coefficient or either density is not finite and > 0;
+// otherwise the public layouts.
+template <bool PAD>
+__global__ void k_faces_from_density(const double* __restrict__ rho, Dims d, double* __restrict__ gx,
+                                     double* __restrict__ gy, double* __restrict__ gz,
+                                     double* __restrict__ partials)
+{
+    const int rx = PAD ? d.nx + 2 : d.nx + 1;
+    const long nfx = (long)d.nz * d.ny * rx;
+    const long nfy = (long)d.nz * (d.ny + 1) * d.nx;
+    const long nfz = (long)(d.nz + 1) * d.ny * d.nx;
+    const long total = nfx + nfy + nfz;
+    const long sz = (long)d.nx * d.ny;
+    double bad = 0.0;
+    for (long f = (long)blockIdx.x * kBlock + threadIdx.x; f < total; f += (long)gridDim.x * kBlock) {
+        long a = -1, bcell = -1;
+        double* out;
+        long o;
+        if (f < nfx) {
+            const int i = (int)(f % rx);
+            const long row = f / rx;
+            if (i > 0 && i < d.nx) { bcell = row * d.nx + i; a = bcell - 1; }
+            out = gx; o = f;
+        } else if (f < nfx + nfy) {
+            const long t = f - nfx;
+            const int j = (int)((t / d.nx) % (d.ny + 1));
+            const int k = (int)(t / ((long)d.nx * (d.ny + 1)));
+            if (j > 0 && j < d.ny) { bcell = ((long)k * d.ny + j) * d.nx + t % d.nx; a = bcell - d.nx; }
+            out = gy; o = t;
+        } else {
+            const long t = f - nfx - nfy;
+            const int k = (int)(t / sz);
+            if (k > 0 && k < d.nz) { bcell = t; a = t - sz; }
+            out = gz; o = t;
+        }
+        double v = 0.0;
+        if (a >= 0) {
+            const double ra = rho[a], rb = rho[bcell];
+            v = 2.0 / (ra + rb);
+            bad += (bad_coeff(v) || bad_coeff(ra) || bad_coeff(rb)) ? 1.0 : 0.0;
+        }
+        out[o] = v;
+    }
+    if (PAD) {
+        bad = block_sum(bad);
+        if (threadIdx.x == 0) partials[blockIdx.x] = bad;
+    }
+}
+
 __global__ void k_divergence(const double* __restrict__ u, const double* __restrict__ v,
                              const double* __restrict__ w, Dims d, double h, double dt, double* __restrict__ b)
 {

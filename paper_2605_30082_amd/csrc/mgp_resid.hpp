@@ -41,14 +41,21 @@ __device__ inline double block_sum_n(double v, double* ws)
 }
 
 // T: arithmetic type of x, b and the coefficients (RES_OUTER: double, with e float).
-template <typename T, int MODE>
+// RHO: the coefficients are not read from the face arrays but formed from the
+// cell density rho as 2/(rho_L + rho_R), the same correctly rounded quotient
+// that defines the stored faces, so the results are identical while 8 bytes
+// per cell replace 24.  rho is staged in LDS like x, with +inf outside the
+// domain, which makes every wall coefficient 2/inf = 0 without a branch.
+template <typename T, int MODE, bool RHO = false>
 __global__ void __launch_bounds__(kResNT)
 k_resid(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz, const T* __restrict__ bb,
         const T* __restrict__ x, const float* __restrict__ e, Dims d, T inv_h2, int zc, int ntx, int nty,
-        T* __restrict__ xout, float* __restrict__ r32, T* __restrict__ coarse, double* __restrict__ partials)
+        T* __restrict__ xout, float* __restrict__ r32, T* __restrict__ coarse, double* __restrict__ partials,
+        const T* __restrict__ rho = nullptr)
 {
     using T2 = typename Vec2<T>::type;
     __shared__ T slot[4 * kResPlane];
+    __shared__ T rslot[RHO ? 4 * kResPlane : 1];
     __shared__ double ws[kResNT / 64];
 
     const int nb = (int)gridDim.x, bid = (int)blockIdx.x;
@@ -75,6 +82,7 @@ k_resid(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict_
     const auto r_bz = make_rsrc(bz, (unsigned)(n_fz(d) * sizeof(T)));
     const auto r_x = make_rsrc(x, (unsigned)(ncell * sizeof(T)));
     const auto r_e = make_rsrc(e ? (const void*)e : (const void*)x, e ? (unsigned)(ncell * sizeof(float)) : 0u);
+    const auto r_rho = make_rsrc(RHO ? (const void*)rho : (const void*)x, RHO ? (unsigned)(ncell * sizeof(T)) : 0u);
     const auto r_null = make_rsrc(x, 0u);
 
     // lane offsets of the pair
@@ -121,6 +129,28 @@ k_resid(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict_
         for (int j = 0; j < kResLoads; ++j)
             if (lidx[j] >= 0) s[lidx[j]] = v[j];
     };
+    // density plane z (RHO): +inf at cells outside the domain
+    const T inf = __builtin_huge_val();
+    auto load_rho = [&](int z, T* w) {
+        if constexpr (RHO) {
+            const bool zv = z >= 0 && z < d.nz;
+            const auto r = zv ? r_rho : r_null;
+            const unsigned so = cplane(z) * psz;
+#pragma unroll
+            for (int j = 0; j < kResLoads; ++j) {
+                const T a = bload1<T>(r, loff[j], so);
+                w[j] = (zv && loff[j] != kOutside) ? a : inf;
+            }
+        }
+    };
+    auto store_rho = [&](int z, const T* w) {
+        if constexpr (RHO) {
+            T* s = rslot + (z & 3) * kResPlane;
+#pragma unroll
+            for (int j = 0; j < kResLoads; ++j)
+                if (lidx[j] >= 0) s[lidx[j]] = w[j];
+        }
+    };
     struct Coef {
         T2 b, bx, by, byu, bzh;
         T bxn;
@@ -128,6 +158,7 @@ k_resid(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict_
     auto load_coef = [&](int z, Coef& C) {
         const unsigned zc_ = cplane(z);
         C.b = bload2<T>(r_b, oc, zc_ * psz);
+        if constexpr (RHO) return;
         C.bx = bload2<T>(r_bx, ofx, zc_ * pfx);
         C.bxn = bload1<T>(r_bx, ofx, zc_ * pfx + 2u * sizeof(T));
         C.by = bload2<T>(r_by, oc, zc_ * pfy);
@@ -137,27 +168,58 @@ k_resid(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict_
 
     // prologue
     const int sbeg = z0;
-    T v[kResLoads];
+    T v[kResLoads], w[RHO ? kResLoads : 1];
     load_plane(sbeg - 1, v);
     store_plane(sbeg - 1, v);
+    load_rho(sbeg - 1, w);
+    store_rho(sbeg - 1, w);
     load_plane(sbeg, v);
     store_plane(sbeg, v);
+    load_rho(sbeg, w);
+    store_rho(sbeg, w);
     load_plane(sbeg + 1, v);
+    load_rho(sbeg + 1, w);
     Coef C, Cn;
     load_coef(sbeg, C);
-    T2 bzl = bload2<T>(r_bz, oc, (unsigned)min(max(sbeg, 0), d.nz) * psz);
+    T2 bzl;
+    if constexpr (!RHO) bzl = bload2<T>(r_bz, oc, (unsigned)min(max(sbeg, 0), d.nz) * psz);
     double acc = 0.0;
     T racc = (T)0;
+    const int li = (row + 1) * kResEX + (xp - x0) + 2;  // LDS index of the pair's even cell
 
     for (int s = sbeg; s < z1; ++s) {
         store_plane(s + 1, v);
         load_plane(s + 2, v);
+        store_rho(s + 1, w);
+        load_rho(s + 2, w);
         load_coef(s + 1, Cn);
         lds_barrier();
         const T* S0 = slot + (s & 3) * kResPlane;
         const T* Sm = slot + ((s - 1) & 3) * kResPlane;
         const T* Sp = slot + ((s + 1) & 3) * kResPlane;
-        const int li = (row + 1) * kResEX + (xp - x0) + 2;  // LDS index of the pair's even cell
+        if constexpr (RHO) {
+            // coefficients of the pair's faces from the densities around it
+            const T* R0 = rslot + (s & 3) * kResPlane;
+            const T2 rc = *reinterpret_cast<const T2*>(R0 + li);
+            const T rw = R0[li - 1], re = R0[li + 2];
+            const T2 rs = *reinterpret_cast<const T2*>(R0 + li - kResEX);
+            const T2 rn = *reinterpret_cast<const T2*>(R0 + li + kResEX);
+            const T2 ru = *reinterpret_cast<const T2*>(rslot + ((s + 1) & 3) * kResPlane + li);
+            if (s == sbeg) {
+                const T2 rd = *reinterpret_cast<const T2*>(rslot + ((s - 1) & 3) * kResPlane + li);
+                bzl.x = (T)2 / (rd.x + rc.x);
+                bzl.y = (T)2 / (rd.y + rc.y);
+            }
+            C.bx.x = (T)2 / (rw + rc.x);
+            C.bx.y = (T)2 / (rc.x + rc.y);
+            C.bxn = (T)2 / (rc.y + re);
+            C.by.x = (T)2 / (rs.x + rc.x);
+            C.by.y = (T)2 / (rs.y + rc.y);
+            C.byu.x = (T)2 / (rc.x + rn.x);
+            C.byu.y = (T)2 / (rc.y + rn.y);
+            C.bzh.x = (T)2 / (rc.x + ru.x);
+            C.bzh.y = (T)2 / (rc.y + ru.y);
+        }
         const T2 c = *reinterpret_cast<const T2*>(S0 + li);
         const T w = S0[li - 1], ea = S0[li + 2];
         const T2 sn = *reinterpret_cast<const T2*>(S0 + li - kResEX);

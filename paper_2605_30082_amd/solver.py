@@ -77,16 +77,23 @@ class Solver:
     record HIP-event durations of the finest-grid kernels.
     """
 
-    def __init__(self, beta_x: torch.Tensor, beta_y: torch.Tensor, beta_z: torch.Tensor, h: float,
+    def __init__(self, beta_x: Optional[torch.Tensor], beta_y: Optional[torch.Tensor] = None,
+                 beta_z: Optional[torch.Tensor] = None, h: float = 1.0,
                  bc: str = "neumann", precision: str = "fp64", pre: int = 2, post: int = 2,
                  max_cycles: int = 100, coarse_max: int = 4, zero_guess: bool = False,
-                 timing: bool = False, stream: Optional[torch.cuda.Stream] = None, method: str = "vcycle"):
+                 timing: bool = False, stream: Optional[torch.cuda.Stream] = None, method: str = "vcycle",
+                 rho: Optional[torch.Tensor] = None):
         self._lib = L.load()
         self._ctx = ctypes.c_void_p(None)
         if bc != "neumann":
             raise MgError(L.MG_EINVAL, f"unsupported boundary condition {bc!r}")
-        nz, ny, nx1 = beta_x.shape
-        self.dims = (nx1 - 1, ny, nz)
+        if rho is not None:
+            nz, ny, nx = rho.shape
+            self.dims = (nx, ny, nz)
+        else:
+            nz, ny, nx1 = beta_x.shape
+            self.dims = (nx1 - 1, ny, nz)
+        self.density = rho is not None
         self.h = float(h)
         self.precision = precision
         shapes = face_shapes(self.dims)
@@ -101,14 +108,26 @@ class Solver:
         self.opts = L.MgOpts(pre, post, max_cycles, coarse_max, prec, flags)
         self._stream = stream
         self._sh = _stream_handle(stream)
-        st = self._lib.mg_setup(ctypes.byref(self._ctx), _ptr(beta_x, "beta_x", shapes[0]),
-                                _ptr(beta_y, "beta_y", shapes[1]), _ptr(beta_z, "beta_z", shapes[2]),
-                                L.dims_arg(self.dims), self.h, L.MG_BC_NEUMANN, ctypes.byref(self.opts),
-                                self._sh)
+        if rho is not None:
+            st = self._lib.mg_setup_density(ctypes.byref(self._ctx), _ptr(rho, "rho", self.cell_shape),
+                                            L.dims_arg(self.dims), self.h, L.MG_BC_NEUMANN,
+                                            ctypes.byref(self.opts), self._sh)
+        else:
+            st = self._lib.mg_setup(ctypes.byref(self._ctx), _ptr(beta_x, "beta_x", shapes[0]),
+                                    _ptr(beta_y, "beta_y", shapes[1]), _ptr(beta_z, "beta_z", shapes[2]),
+                                    L.dims_arg(self.dims), self.h, L.MG_BC_NEUMANN, ctypes.byref(self.opts),
+                                    self._sh)
         if st != L.MG_OK:
             self._ctx = ctypes.c_void_p(None)
             raise MgError(st, L.last_error(None))
-        self.device = beta_x.device
+        self.device = (rho if rho is not None else beta_x).device
+
+    @classmethod
+    def from_density(cls, rho: torch.Tensor, h: float, **kw) -> "Solver":
+        """Hierarchy for the coefficients 2/(rho_L + rho_R) of a cell density
+        (mg_setup_density): same results as the faces of faces_from_density(rho),
+        with the finest FP64 residual passes reading rho instead of three face arrays."""
+        return cls(None, None, None, h, rho=rho, **kw)
 
     # -- lifetime ---------------------------------------------------------------
     def close(self) -> None:
@@ -155,6 +174,10 @@ class Solver:
         shapes = face_shapes(self.dims)
         self._check(self._lib.mg_update(self._ctx, _ptr(beta_x, "beta_x", shapes[0]),
                                         _ptr(beta_y, "beta_y", shapes[1]), _ptr(beta_z, "beta_z", shapes[2])))
+
+    def update_density(self, rho: torch.Tensor) -> None:
+        """New cell density (contexts made from a density only; no allocation)."""
+        self._check(self._lib.mg_update_density(self._ctx, _ptr(rho, "rho", self.cell_shape)))
 
     # -- solves -----------------------------------------------------------------
     def solve(self, rhs: torch.Tensor, tol: float = 1e-10, p: Optional[torch.Tensor] = None,
@@ -258,6 +281,29 @@ def faces_from_vof(f_drop: torch.Tensor, f_film: torch.Tensor, rho_drop: float, 
     st = L.load().mg_faces_from_vof(_ptr(f_drop, "f_drop"), _ptr(f_film, "f_film", f_drop.shape),
                                     L.dims_arg(dims), float(rho_drop), float(rho_film), float(rho_gas),
                                     *[_ptr(a, "beta") for a in out], _stream_handle(stream))
+    L.check(st)
+    return tuple(out)
+
+
+def density_from_vof(f_drop: torch.Tensor, f_film: torch.Tensor, rho_drop: float, rho_film: float,
+                     rho_gas: float, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Cell density sum_i rho_i f_i from the two liquid VOF fractions (GPU)."""
+    nz, ny, nx = f_drop.shape
+    rho = torch.empty_like(f_drop)
+    st = L.load().mg_density_from_vof(_ptr(f_drop, "f_drop"), _ptr(f_film, "f_film", f_drop.shape),
+                                      L.dims_arg((nx, ny, nz)), float(rho_drop), float(rho_film),
+                                      float(rho_gas), _ptr(rho, "rho"), _stream_handle(stream))
+    L.check(st)
+    return rho
+
+
+def faces_from_density(rho: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+    """Face coefficients 2/(rho_L + rho_R), 0 on walls, from a cell density (GPU)."""
+    nz, ny, nx = rho.shape
+    shapes = face_shapes((nx, ny, nz))
+    out = [torch.empty(s, dtype=torch.float64, device=rho.device) for s in shapes]
+    st = L.load().mg_faces_from_density(_ptr(rho, "rho"), L.dims_arg((nx, ny, nz)),
+                                        *[_ptr(a, "beta") for a in out], _stream_handle(stream))
     L.check(st)
     return tuple(out)
 

@@ -103,6 +103,25 @@ def test_setup_rejects_bad_arguments_before_any_device_work():
     assert lib.mg_last_error(None) is not None
 
 
+def test_density_setup_rejects_bad_arguments_before_any_device_work():
+    lib = L.load()
+    ctx = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    opts = L.MgOpts(2, 2, 100, 4, L.MG_PREC_MIXED, 0)
+    st = lib.mg_setup_density(ctypes.byref(ctx), None, L.dims_arg((8, 8, 8)), 1 / 8, 0, ctypes.byref(opts), None)
+    assert st == L.MG_EINVAL and not ctx.value and L.last_error(None) == "NULL argument"
+    st = lib.mg_setup_density(ctypes.byref(ctx), fake, L.dims_arg((7, 8, 8)), 1 / 8, 0, ctypes.byref(opts), None)
+    assert st == L.MG_EINVAL and "cannot be coarsened" in L.last_error(None)
+    st = lib.mg_setup_density(ctypes.byref(ctx), fake, L.dims_arg((8, 8, 8)), 1 / 8, 3, ctypes.byref(opts), None)
+    assert st == L.MG_EINVAL and "MG_BC_NEUMANN" in L.last_error(None)
+    assert lib.mg_update_density(None, fake) == L.MG_EINVAL
+    assert lib.mg_density_from_vof(fake, fake, L.dims_arg((4, 0, 4)), 1.0, 1.0, 1.0, fake, None) == L.MG_EINVAL
+    assert lib.mg_density_from_vof(fake, fake, L.dims_arg((4, 4, 4)), 1.0, -1.0, 1.0, fake, None) == L.MG_EINVAL
+    assert lib.mg_density_from_vof(fake, None, L.dims_arg((4, 4, 4)), 1.0, 1.0, 1.0, fake, None) == L.MG_EINVAL
+    assert lib.mg_faces_from_density(fake, L.dims_arg((4, 4, 0)), fake, fake, fake, None) == L.MG_EINVAL
+    assert lib.mg_faces_from_density(None, L.dims_arg((4, 4, 4)), fake, fake, fake, None) == L.MG_EINVAL
+
+
 def test_context_free_calls_validate_arguments():
     lib = L.load()
     fake = ctypes.c_void_p(0x1000)

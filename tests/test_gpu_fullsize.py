@@ -13,6 +13,7 @@ import os
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
 import refs
@@ -133,6 +134,27 @@ def test_solves_512(big):
     assert st.cycles == meta["tol12_cycles"]
     assert np.sqrt(np.mean(d ** 2)) < 1e-11 * rms and np.abs(d).max() < 1e-10 * rms
     s.close()
+
+
+def test_density_context_512(big):
+    """The benchmark's default configuration: the hierarchy built from the cell
+    density.  Its solves equal the face-array solves bit for bit, in both precisions."""
+    wl, gb, gd, ob, od = big
+    meta, idx, val = read_golden()
+    rho = S.density_from_vof(T(wl.f_drop), T(wl.f_film), wl.rho_drop, wl.rho_film, wl.rho_gas)
+    for precision in ("mixed", "fp64"):
+        kw = dict(precision=precision, zero_guess=True)
+        with S.Solver.from_density(rho, wl.h, **kw) as s:
+            pd, std = s.solve(gd, 1e-10)
+        with S.Solver(*gb, wl.h, **kw) as s:
+            pf, stf = s.solve(gd, 1e-10)
+        note(f"512^3 density context {precision}: cycles {std.cycles} rr {std.rel_res:.3e}")
+        assert torch.equal(pd, pf) and std.hist == stf.hist
+        assert std.cycles == meta["tol10_cycles"] and std.rel_res <= 1e-10
+        d = N(pd).ravel()[idx] - val["tol10"]
+        rms = meta["tol10_norm2"] / np.sqrt(512 ** 3)
+        assert np.sqrt(np.mean(d ** 2)) < (1e-11 if precision == "fp64" else 1e-9) * rms
+        del pd, pf
 
 
 def test_layered_film_512_exact():

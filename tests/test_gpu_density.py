@@ -84,6 +84,11 @@ def test_density_context_kernels_identical(dims):
     for precision in ("fp64", "mixed"):
         got = sd.residual_restrict(T(b), T(p), level=0, precision=precision)
         assert torch.equal(got, sf.residual_restrict(T(b), T(p), level=0, precision=precision))
+        for order in (0, 1):
+            for sweeps in (1, 2):
+                got = sd.smooth(T(b), T(p), level=0, sweeps=sweeps, order=order, precision=precision)
+                ref = sf.smooth(T(b), T(p), level=0, sweeps=sweeps, order=order, precision=precision)
+                assert torch.equal(got, ref), (precision, order, sweeps)
     assert sd.residual_norm2(T(b), T(p)) == sf.residual_norm2(T(b), T(p))
     # the density kernels against the oracle's definition
     ob = oracle.face_coeffs(rho)
@@ -92,6 +97,11 @@ def test_density_context_kernels_identical(dims):
     assert max_rel(got, oracle.restrict(r)) < 1e-13
     n2 = sd.residual_norm2(T(b), T(p))
     assert abs(n2 - float(np.sum(r * r))) <= 1e-12 * float(np.sum(r * r))
+    ref = p
+    for colour in (0, 1):
+        ref = oracle.rbgs_half(ob, b, ref, h, colour)
+    got = N(sd.smooth(T(b), T(p), level=0, sweeps=1, order=0, precision="fp64"))
+    assert max_rel(got, ref) < 1e-13
     sd.close()
     sf.close()
 

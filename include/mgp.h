@@ -259,6 +259,19 @@ int mg_faces_from_density(const double *rho, const int dims[3], double *beta_x, 
                           double *beta_z, void *hip_stream);
 
 /*
+ * mg_density_grad -- gradient of a loss with respect to the cell density, given
+ * its gradient with respect to the face coefficients (e.g. from mg_face_grad):
+ * the chain rule through mg_faces_from_density,
+ *   d beta_f / d rho_L = d beta_f / d rho_R = -2 / (rho_L + rho_R)^2,
+ * summed over each cell's interior faces (each product rounded as written).
+ *   rho, g_rho      device cell arrays (g_rho written).
+ *   g_x, g_y, g_z   device face arrays (public layouts); wall entries ignored.
+ *   dims host int[3].  MG_EINVAL on bad arguments.
+ */
+int mg_density_grad(const double *rho, const int dims[3], const double *g_x, const double *g_y,
+                    const double *g_z, double *g_rho, void *hip_stream);
+
+/*
  * mg_divergence -- b = div_h(u, v, w) / dt for MAC face velocities
  * (u: x-face layout, v: y-face layout, w: z-face layout; b: cell layout).
  */

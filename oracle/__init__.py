@@ -65,6 +65,7 @@ def lib():
             "or_divergence": (None, [dp, dp, dp, I, I, I, D, D, dp]),
             "or_velocity_correct": (None, [dp, dp, dp, I, I, I, D, D, dp, dp, dp, dp]),
             "or_vof_grad": (I, [dp, dp, I, I, I, D, D, D, dp, dp, dp, dp, dp]),
+            "or_density_grad": (None, [dp, I, I, I, dp, dp, dp, dp]),
             "or_apply": (None, [dp, dp, dp, I, I, I, D, dp, dp]),
             "or_residual": (None, [dp, dp, dp, I, I, I, D, dp, dp, dp]),
             "or_rbgs_half": (None, [dp, dp, dp, I, I, I, D, dp, dp, I]),
@@ -154,6 +155,16 @@ def velocity_correct(beta, p, u, v, w, h: float, dt: float = 1.0):
     lib().or_velocity_correct(_p(bx), _p(by), _p(bz), nx, ny, nz, h, dt, _p(p),
                               _p(u2), _p(v2), _p(w2))
     return u2, v2, w2
+
+
+def density_grad(rho, g_beta) -> np.ndarray:
+    """dL/drho from dL/dbeta (face layouts) through beta_f = 2/(rho_L + rho_R)."""
+    r = _c(rho)
+    gx, gy, gz = (_c(a) for a in g_beta)
+    nx, ny, nz = _dims(r)
+    out = np.empty_like(r)
+    lib().or_density_grad(_p(r), nx, ny, nz, _p(gx), _p(gy), _p(gz), _p(out))
+    return out
 
 
 def vof_grad(f_drop, f_film, rho_drop: float, rho_film: float, rho_gas: float, g_beta):

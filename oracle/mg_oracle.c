@@ -151,28 +151,18 @@ void or_velocity_correct(const double *bx, const double *by, const double *bz,
                 w[FZ(i, j, k)] -= dt * bz[FZ(i, j, k)] * (p[CELL(i, j, k)] - p[CELL(i, j, k - 1)]) / h;
 }
 
-/* Gradient of a loss with respect to the VOF fractions, given its gradient
- * g_f with respect to the face coefficients (face layouts).  Chain rule
- * through the mixture density (Sec. 2, eq. "property_calculation", with the
- * gas fraction max(0, 1 - f_drop - f_film)) and beta_f = 2/(rho_L + rho_R):
- *   d beta_f / d rho_L = d beta_f / d rho_R = -2 / (rho_L + rho_R)^2,
- *   d rho / d f_drop = rho_drop - rho_gas (rho_drop where the gas fraction
- *   is clamped, i.e. 1 - f_drop - f_film < 0), likewise for f_film.
- * Every interior face adds its share to both of its cells. */
-int or_vof_grad(const double *f_drop, const double *f_film, int nx, int ny, int nz,
-                double rho_drop, double rho_film, double rho_gas,
-                const double *gx, const double *gy, const double *gz,
-                double *g_drop, double *g_film)
+/* Gradient of a loss with respect to the cell density, given its gradient g_f
+ * with respect to the face coefficients beta_f = 2/(rho_L + rho_R) (face
+ * layouts):  d beta_f / d rho_L = d beta_f / d rho_R = -2 / (rho_L + rho_R)^2.
+ * Every interior face adds its share to both of its cells; wall entries of
+ * g are ignored. */
+void or_density_grad(const double *rho, int nx, int ny, int nz,
+                     const double *gx, const double *gy, const double *gz, double *grho)
 {
     long n = (long)nx * ny * nz, c;
     int i, j, k;
-    double *rho = malloc(sizeof(double) * n), *grho = calloc(n, sizeof(double));
-    if (!rho || !grho) {
-        free(rho);
-        free(grho);
-        return OR_ENOMEM;
-    }
-    or_density(f_drop, f_film, n, rho_drop, rho_film, rho_gas, rho);
+    for (c = 0; c < n; c++)
+        grho[c] = 0.0;
     for (k = 0; k < nz; k++)
         for (j = 0; j < ny; j++)
             for (i = 1; i < nx; i++) {
@@ -197,6 +187,28 @@ int or_vof_grad(const double *f_drop, const double *f_film, int nx, int ny, int 
                 grho[CELL(i, j, k - 1)] += d;
                 grho[CELL(i, j, k)] += d;
             }
+}
+
+/* Gradient of a loss with respect to the VOF fractions, given its gradient
+ * g_f with respect to the face coefficients (face layouts).  Chain rule
+ * through the mixture density (Sec. 2, eq. "property_calculation", with the
+ * gas fraction max(0, 1 - f_drop - f_film)) and or_density_grad:
+ *   d rho / d f_drop = rho_drop - rho_gas (rho_drop where the gas fraction
+ *   is clamped, i.e. 1 - f_drop - f_film < 0), likewise for f_film. */
+int or_vof_grad(const double *f_drop, const double *f_film, int nx, int ny, int nz,
+                double rho_drop, double rho_film, double rho_gas,
+                const double *gx, const double *gy, const double *gz,
+                double *g_drop, double *g_film)
+{
+    long n = (long)nx * ny * nz, c;
+    double *rho = malloc(sizeof(double) * n), *grho = malloc(sizeof(double) * n);
+    if (!rho || !grho) {
+        free(rho);
+        free(grho);
+        return OR_ENOMEM;
+    }
+    or_density(f_drop, f_film, n, rho_drop, rho_film, rho_gas, rho);
+    or_density_grad(rho, nx, ny, nz, gx, gy, gz, grho);
     for (c = 0; c < n; c++) {
         double gas = (1.0 - f_drop[c] - f_film[c] < 0.0) ? 0.0 : rho_gas;
         g_drop[c] = grho[c] * (rho_drop - gas);

@@ -64,6 +64,7 @@ SIGNATURES = {
     "mg_divergence": (_I, [_D, _D, _D, _DIMS, _F, _F, _D, ctypes.c_void_p]),
     "mg_density_from_vof": (_I, [_D, _D, _DIMS, _F, _F, _F, _D, ctypes.c_void_p]),
     "mg_faces_from_density": (_I, [_D, _DIMS, _D, _D, _D, ctypes.c_void_p]),
+    "mg_density_grad": (_I, [_D, _DIMS, _D, _D, _D, _D, ctypes.c_void_p]),
     "mg_vof_grad": (_I, [_D, _D, _DIMS, _F, _F, _F, _D, _D, _D, _D, _D, ctypes.c_void_p]),
     "mg_velocity_correct": (_I, [_D, _D, _D, _D, _DIMS, _F, _F, _D, _D, _D, ctypes.c_void_p]),
     "mg_plan_levels": (_I, [_DIMS, _I]),

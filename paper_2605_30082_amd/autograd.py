@@ -11,7 +11,8 @@ p is recomputed in the backward pass from the saved (rhs, beta) unless
 save_p=True; no V-cycle state is stored.
 
 faces_from_vof chains the gradient one step further, to the VOF fractions the
-face coefficients are built from (mixture density, then harmonic-mean faces).
+face coefficients are built from (mixture density, then harmonic-mean faces);
+faces_from_density to a cell density.
 """
 from __future__ import annotations
 
@@ -87,3 +88,24 @@ class FacesFromVof(torch.autograd.Function):
 def faces_from_vof(f_drop, f_film, rho_drop: float, rho_film: float, rho_gas: float):
     """Differentiable face coefficients (beta_x, beta_y, beta_z) from the VOF fractions."""
     return FacesFromVof.apply(f_drop, f_film, rho_drop, rho_film, rho_gas)
+
+
+class FacesFromDensity(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rho):
+        rho = rho.contiguous()
+        ctx.save_for_backward(rho)
+        return _S.faces_from_density(rho)
+
+    @staticmethod
+    def backward(ctx, g_x, g_y, g_z):
+        (rho,) = ctx.saved_tensors
+        shapes = _S.face_shapes(tuple(reversed(rho.shape)))
+        grads = [torch.zeros(s, dtype=torch.float64, device=rho.device) if g is None else g.contiguous()
+                 for g, s in zip((g_x, g_y, g_z), shapes)]
+        return _S.density_grad(rho, *grads)
+
+
+def faces_from_density(rho):
+    """Differentiable face coefficients (beta_x, beta_y, beta_z) = 2/(rho_L + rho_R) from a cell density."""
+    return FacesFromDensity.apply(rho)

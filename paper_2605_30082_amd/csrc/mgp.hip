@@ -1109,6 +1109,18 @@ int mg_faces_from_density(const double* rho, const int dims[3], double* beta_x, 
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 
+int mg_density_grad(const double* rho, const int dims[3], const double* g_x, const double* g_y, const double* g_z,
+                    double* g_rho, void* hip_stream)
+{
+    if (!rho || !dims || !g_x || !g_y || !g_z || !g_rho) return MG_EINVAL;
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return MG_EINVAL;
+    const Dims d{dims[0], dims[1], dims[2]};
+    const long n = (long)d.nx * d.ny * d.nz;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    k_density_grad<<<grid_for(n), kBlock, 0, s>>>(rho, d, g_x, g_y, g_z, g_rho);
+    return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
+}
+
 int mg_divergence(const double* u, const double* v, const double* w, const int dims[3], double h, double dt,
                   double* b, void* hip_stream)
 {

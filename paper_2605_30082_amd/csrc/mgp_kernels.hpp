@@ -738,6 +738,36 @@ __global__ void k_vof_grad(const double* __restrict__ fd, const double* __restri
     }
 }
 
+// dL/drho_c = sum over the cell's interior faces f of dL/dbeta_f * (-2 / (rho_c + rho_nb)^2),
+// the derivative of beta_f = 2/(rho_L + rho_R); g in the public face layouts.
+__global__ void k_density_grad(const double* __restrict__ rho, Dims d, const double* __restrict__ gx,
+                               const double* __restrict__ gy, const double* __restrict__ gz,
+                               double* __restrict__ grho)
+{
+#pragma clang fp contract(off)
+    const long n = (long)d.nx * d.ny * d.nz;
+    const long sz = (long)d.nx * d.ny;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
+        int i, j, k;
+        cell_of(c, d, i, j, k);
+        const double rc = rho[c];
+        const long fx = ((long)k * d.ny + j) * (d.nx + 1) + i;
+        const long fy = ((long)k * (d.ny + 1) + j) * d.nx + i;
+        double acc = 0.0;
+        auto face = [&](long nb, double g) {
+            const double s = rc + rho[nb];
+            acc += g * (-2.0 / (s * s));
+        };
+        if (i > 0) face(c - 1, gx[fx]);
+        if (i < d.nx - 1) face(c + 1, gx[fx + 1]);
+        if (j > 0) face(c - d.nx, gy[fy]);
+        if (j < d.ny - 1) face(c + d.nx, gy[fy + d.nx]);
+        if (k > 0) face(c - sz, gz[c]);
+        if (k < d.nz - 1) face(c + sz, gz[c + sz]);
+        grho[c] = acc;
+    }
+}
+
 // u_f -= dt * beta_f * (p_R - p_L) / h on interior faces of the public face
 // layouts (evaluated left to right, no contraction); one thread per face.
 __global__ void k_velocity_correct(const double* __restrict__ bx, const double* __restrict__ by,

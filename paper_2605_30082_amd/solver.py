@@ -308,6 +308,19 @@ def faces_from_density(rho: torch.Tensor, stream: Optional[torch.cuda.Stream] = 
     return tuple(out)
 
 
+def density_grad(rho: torch.Tensor, g_x: torch.Tensor, g_y: torch.Tensor, g_z: torch.Tensor,
+                 stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """dL/drho from dL/dbeta on the faces, through beta_f = 2/(rho_L + rho_R) (GPU)."""
+    nz, ny, nx = rho.shape
+    shapes = face_shapes((nx, ny, nz))
+    g = torch.empty_like(rho)
+    st = L.load().mg_density_grad(_ptr(rho, "rho"), L.dims_arg((nx, ny, nz)), _ptr(g_x, "g_x", shapes[0]),
+                                  _ptr(g_y, "g_y", shapes[1]), _ptr(g_z, "g_z", shapes[2]), _ptr(g, "g_rho"),
+                                  _stream_handle(stream))
+    L.check(st)
+    return g
+
+
 def divergence(u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, h: float, dt: float = 1.0,
                stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
     """b = div_h(u, v, w)/dt on the MAC grid (GPU)."""

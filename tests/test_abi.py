@@ -120,6 +120,8 @@ def test_density_setup_rejects_bad_arguments_before_any_device_work():
     assert lib.mg_density_from_vof(fake, None, L.dims_arg((4, 4, 4)), 1.0, 1.0, 1.0, fake, None) == L.MG_EINVAL
     assert lib.mg_faces_from_density(fake, L.dims_arg((4, 4, 0)), fake, fake, fake, None) == L.MG_EINVAL
     assert lib.mg_faces_from_density(None, L.dims_arg((4, 4, 4)), fake, fake, fake, None) == L.MG_EINVAL
+    assert lib.mg_density_grad(fake, L.dims_arg((0, 4, 4)), fake, fake, fake, fake, None) == L.MG_EINVAL
+    assert lib.mg_density_grad(fake, L.dims_arg((4, 4, 4)), fake, None, fake, fake, None) == L.MG_EINVAL
 
 
 def test_context_free_calls_validate_arguments():

@@ -188,3 +188,49 @@ def test_gradient_reaches_vof_fractions():
         b[idx] -= eps
         fdiff = (loss(a, wl.f_film) - loss(b, wl.f_film)) / (2 * eps)
         assert abs(fdiff - gd[idx]) <= 1e-4 * abs(gd[idx]) + 1e-6 * gmax, (idx, fdiff, gd[idx])
+
+
+def test_density_grad_kernel_matches_oracle():
+    dims = (37, 22, 13)
+    nx, ny, nz = dims
+    g = np.random.default_rng(43)
+    rho = np.where(g.random((nz, ny, nx)) < 0.4, 1.2, 1000.0) * g.uniform(0.5, 1.0, (nz, ny, nx))
+    gb = [g.standard_normal(s) for s in S.face_shapes(dims)]
+    got = N(S.density_grad(T(rho), *[T(a) for a in gb]))
+    assert max_rel(got, oracle.density_grad(rho, gb)) < 1e-13
+
+
+def test_gradient_reaches_density():
+    """loss = sum(w p), p from the face coefficients of a cell density: the GPU chain
+    (adjoint solve, face gradient, density gradient) against the oracle's chain and
+    against central differences of the oracle's composition at interface cells."""
+    from paper_2605_30082_amd.autograd import faces_from_density
+    wl = W.drop_film_workload(16)
+    w = W.loss_weights(wl.dims)
+    orho = oracle.density(wl.f_drop, wl.f_film, wl.rho_drop, wl.rho_film, wl.rho_gas)
+    rho = leaf(T(orho))
+    rhs = S.divergence(T(wl.u), T(wl.v), T(wl.w), wl.h, wl.dt)
+    bx, by, bz = faces_from_density(rho)
+    p = poisson_solve(rhs, bx, by, bz, wl.h, tol=1e-12)
+    (T(w) * p).sum().backward()
+    got = N(rho.grad)
+    ob = oracle.face_coeffs(orho)
+    od = oracle.divergence(wl.u, wl.v, wl.w, wl.h, wl.dt)
+    _, _, gbeta = oracle.gradients(ob, od, w, wl.h, tol=1e-13)
+    assert rel_l2(got, oracle.density_grad(orho, gbeta)) < 1e-8
+    p0 = oracle.solve(ob, od, wl.h, tol=1e-13).p
+
+    def loss(r):
+        return float(np.sum(w * oracle.solve(oracle.face_coeffs(r), od, wl.h, tol=1e-13, p0=p0).p))
+
+    gmax = np.abs(got).max()
+    cand = np.argwhere((orho > 5.0) & (orho < 900.0))
+    pick = np.random.default_rng(44).choice(len(cand), 4, replace=False)
+    for t in pick:
+        idx = tuple(cand[t])
+        eps = 1e-6 * orho[idx]
+        a, b = orho.copy(), orho.copy()
+        a[idx] += eps
+        b[idx] -= eps
+        fdiff = (loss(a) - loss(b)) / (2 * eps)
+        assert abs(fdiff - got[idx]) <= 1e-4 * abs(got[idx]) + 1e-6 * gmax, (idx, fdiff, got[idx])

@@ -611,3 +611,38 @@ def test_failure_statuses(oracle_mod):
     assert r.status == oracle_mod.OR_EINVAL
     zero = oracle_mod.solve(beta, np.full_like(b, 2.0), wl.h)
     assert zero.cycles == 0 and np.all(zero.p == 0)
+
+
+def test_density_gradient_uniform_closed_form(oracle_mod):
+    # uniform rho: every interior face has d beta / d rho = -2/(2 rho)^2 = -1/(2 rho^2) on each side;
+    # unit weights on every face, walls included (they must be ignored)
+    dims = (4, 3, 5)
+    nx, ny, nz = dims
+    rho = np.full((nz, ny, nx), 7.0)
+    w = [np.ones(s) for s in ((nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx))]
+    got = oracle_mod.density_grad(rho, w)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    n_int = ((i > 0).astype(int) + (i < nx - 1) + (j > 0) + (j < ny - 1) + (k > 0) + (k < nz - 1))
+    np.testing.assert_allclose(got, -n_int / (2 * 7.0 ** 2), rtol=1e-15)
+
+
+def test_density_gradient_matches_finite_differences(oracle_mod):
+    # J(rho) = sum_f w_f beta_f(rho) on a ragged grid with an 800x density contrast
+    dims = (5, 4, 3)
+    nx, ny, nz = dims
+    g = rng(19)
+    rho = np.where(g.random((nz, ny, nx)) < 0.5, 1.2, 960.0) * g.uniform(0.9, 1.1, (nz, ny, nx))
+    w = [g.standard_normal(s) for s in ((nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx))]
+
+    def J(r):
+        return sum(float(np.sum(x * y)) for x, y in zip(w, oracle_mod.face_coeffs(r)))
+
+    got = oracle_mod.density_grad(rho, w)
+    for c in range(rho.size):
+        idx = np.unravel_index(c, rho.shape)
+        eps = 1e-6 * rho[idx]
+        rp, rm = rho.copy(), rho.copy()
+        rp[idx] += eps
+        rm[idx] -= eps
+        fdiff = (J(rp) - J(rm)) / (2 * eps)
+        assert abs(fdiff - got[idx]) <= 1e-6 * abs(got[idx]) + 1e-9 * np.abs(got).max(), (idx, fdiff, got[idx])

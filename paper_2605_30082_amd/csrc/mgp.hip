@@ -462,10 +462,15 @@ int fcg_step(mg_ctx* c, const TZ* z, double* x, float* r32, bool first, double d
         const ResGeom g = res_geom(F.d);
         nparts = g.blocks;
         double* dnew = c->fd == c->fd_buf[0] ? c->fd_buf[1] : c->fd_buf[0];
-        k_fcg_dir_apply<TZ><<<g.blocks, kResNT, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, z, c->fd, c->fr, F.d,
-                                                                 1.0 / (F.h * F.h), c->scal, kSlotZQ, dq_prev,
-                                                                 first ? 1 : 0, g.zc, g.ntx, g.nty, dnew, c->fq,
-                                                                 c->partials);
+        if (c->use_rho)
+            k_fcg_dir_apply<TZ, true><<<g.blocks, kResNT, 0, c->stream>>>(
+                F.f64.bx, F.f64.by, F.f64.bz, z, c->fd, c->fr, F.d, 1.0 / (F.h * F.h), c->scal, kSlotZQ, dq_prev,
+                first ? 1 : 0, g.zc, g.ntx, g.nty, dnew, c->fq, c->partials, c->rho);
+        else
+            k_fcg_dir_apply<TZ><<<g.blocks, kResNT, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, z, c->fd, c->fr,
+                                                                     F.d, 1.0 / (F.h * F.h), c->scal, kSlotZQ,
+                                                                     dq_prev, first ? 1 : 0, g.zc, g.ntx, g.nty, dnew,
+                                                                     c->fq, c->partials);
         CHECK_LAUNCH(c);
         c->fd = dnew;
     } else {

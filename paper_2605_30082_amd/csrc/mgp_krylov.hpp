@@ -89,16 +89,20 @@ __global__ void k_fcg_update(double* __restrict__ x, double* __restrict__ r, con
 // dq_prev; first: d = z), with its 1-cell ring recomputed rather than
 // exchanged.  Each thread writes d and q for its pair and accumulates (d, q)
 // into partials[0, gridDim) and (d, r) into partials[gridDim, 2 gridDim).
-template <typename TZ>
+// RHO: coefficients formed from the cell density rho (staged like d), as in
+// the density-fed instances of k_resid.
+template <typename TZ, bool RHO = false>
 __global__ void __launch_bounds__(kResNT)
 k_fcg_dir_apply(const double* __restrict__ bx, const double* __restrict__ by, const double* __restrict__ bz,
                 const TZ* __restrict__ zv, const double* __restrict__ dprev, const double* __restrict__ r, Dims d,
                 double inv_h2, const double* __restrict__ scal, int zq_slot, double dq_prev, int first, int zc,
-                int ntx, int nty, double* __restrict__ dout, double* __restrict__ q, double* __restrict__ partials)
+                int ntx, int nty, double* __restrict__ dout, double* __restrict__ q, double* __restrict__ partials,
+                const double* __restrict__ rho = nullptr)
 {
     using T = double;
     using T2 = double2;
     __shared__ T slot[4 * kResPlane];
+    __shared__ T rslot[RHO ? 4 * kResPlane : 1];
     __shared__ double ws[kResNT / 64];
 
     const int nb = (int)gridDim.x, bid = (int)blockIdx.x;
@@ -127,6 +131,7 @@ k_fcg_dir_apply(const double* __restrict__ bx, const double* __restrict__ by, co
     const auto r_bz = make_rsrc(bz, (unsigned)(n_fz(d) * sizeof(T)));
     const auto r_z = make_rsrc(zv, (unsigned)(ncell * sizeof(TZ)));
     const auto r_dp = make_rsrc(dprev, first ? 0u : (unsigned)(ncell * sizeof(T)));
+    const auto r_rho = make_rsrc(RHO ? (const void*)rho : (const void*)zv, RHO ? (unsigned)(ncell * sizeof(T)) : 0u);
     const auto r_null = make_rsrc(zv, 0u);
 
     const unsigned oc = (unsigned)(yc * d.nx + xc) * sizeof(T);
@@ -164,6 +169,17 @@ k_fcg_dir_apply(const double* __restrict__ bx, const double* __restrict__ by, co
         for (int j = 0; j < kResLoads; ++j)
             if (lidx[j] >= 0) sl[lidx[j]] = v[j];
     };
+    auto load_rho = [&](int zz, T* w) {
+        if constexpr (RHO) rho_plane_load<T>(r_rho, r_null, loff, zz, d.nz, psz, w);
+    };
+    auto store_rho = [&](int zz, const T* w) {
+        if constexpr (RHO) {
+            T* sl = rslot + (zz & 3) * kResPlane;
+#pragma unroll
+            for (int j = 0; j < kResLoads; ++j)
+                if (lidx[j] >= 0) sl[lidx[j]] = w[j];
+        }
+    };
     struct Coef {
         T2 r, bx, by, byu, bzh;
         T bxn;
@@ -171,6 +187,7 @@ k_fcg_dir_apply(const double* __restrict__ bx, const double* __restrict__ by, co
     auto load_coef = [&](int zz, Coef& C) {
         const unsigned zp = cplane(zz);
         C.r = bload2<T>(r_r, oc, zp * psz);
+        if constexpr (RHO) return;
         C.bx = bload2<T>(r_bx, ofx, zp * pfx);
         C.bxn = bload1<T>(r_bx, ofx, zp * pfx + 2u * sizeof(T));
         C.by = bload2<T>(r_by, oc, zp * pfy);
@@ -178,26 +195,44 @@ k_fcg_dir_apply(const double* __restrict__ bx, const double* __restrict__ by, co
         C.bzh = bload2<T>(r_bz, oc, (unsigned)min(max(zz + 1, 0), d.nz) * psz);
     };
 
-    T v[kResLoads];
+    T v[kResLoads], w[RHO ? kResLoads : 1];
     load_plane(z0 - 1, v);
     store_plane(z0 - 1, v);
+    load_rho(z0 - 1, w);
+    store_rho(z0 - 1, w);
     load_plane(z0, v);
     store_plane(z0, v);
+    load_rho(z0, w);
+    store_rho(z0, w);
     load_plane(z0 + 1, v);
+    load_rho(z0 + 1, w);
     Coef C, Cn;
     load_coef(z0, C);
-    T2 bzl = bload2<T>(r_bz, oc, (unsigned)min(max(z0, 0), d.nz) * psz);
+    T2 bzl;
+    if constexpr (!RHO) bzl = bload2<T>(r_bz, oc, (unsigned)min(max(z0, 0), d.nz) * psz);
     double dq = 0.0, dr = 0.0;
+    const int li = (row + 1) * kResEX + (xp - x0) + 2;
 
     for (int s = z0; s < z1; ++s) {
         store_plane(s + 1, v);
         load_plane(s + 2, v);
+        store_rho(s + 1, w);
+        load_rho(s + 2, w);
         load_coef(s + 1, Cn);
         lds_barrier();
         const T* S0 = slot + (s & 3) * kResPlane;
         const T* Sm = slot + ((s - 1) & 3) * kResPlane;
         const T* Sp = slot + ((s + 1) & 3) * kResPlane;
-        const int li = (row + 1) * kResEX + (xp - x0) + 2;
+        if constexpr (RHO) {
+            const T* R0 = rslot + (s & 3) * kResPlane;
+            if (s == z0) {
+                const T2 rd = *reinterpret_cast<const T2*>(rslot + ((s - 1) & 3) * kResPlane + li);
+                const T2 rc = *reinterpret_cast<const T2*>(R0 + li);
+                bzl.x = (T)2 / (rd.x + rc.x);
+                bzl.y = (T)2 / (rd.y + rc.y);
+            }
+            rho_pair_faces<T, T2>(R0, rslot + ((s + 1) & 3) * kResPlane, li, C.bx, C.bxn, C.by, C.byu, C.bzh);
+        }
         const T2 c = *reinterpret_cast<const T2*>(S0 + li);
         const T w = S0[li - 1], ea = S0[li + 2];
         const T2 sn = *reinterpret_cast<const T2*>(S0 + li - kResEX);

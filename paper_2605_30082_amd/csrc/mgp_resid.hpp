@@ -26,6 +26,46 @@ constexpr int kResEY = kResTY + 2;          // LDS rows: y0-1 .. y0+TY
 constexpr int kResPlane = kResEX * kResEY;
 constexpr int kResLoads = (66 * kResEY + kResNT - 1) / kResNT;  // x0-1 .. x0+64 of each row
 
+// Density-fed coefficients (passes over the finest grid of a density context):
+// density planes are staged in LDS on the iterate's footprint with +inf at
+// cells outside the domain, and a pair's face coefficients are formed as the
+// correctly rounded 2/(rho_L + rho_R) that defines the face arrays, so a wall
+// coefficient comes out as 2/inf = 0 without a branch.
+template <typename T>
+__device__ inline void rho_plane_load(__amdgpu_buffer_rsrc_t r_rho, __amdgpu_buffer_rsrc_t r_null, const unsigned* loff,
+                                      int z, int nz, unsigned psz, T* w)
+{
+    const bool zv = z >= 0 && z < nz;
+    const auto r = zv ? r_rho : r_null;
+    const unsigned so = (unsigned)min(max(z, 0), nz - 1) * psz;
+#pragma unroll
+    for (int j = 0; j < kResLoads; ++j) {
+        const T a = bload1<T>(r, loff[j], so);
+        w[j] = (zv && loff[j] != kOutside) ? a : (T)__builtin_huge_val();
+    }
+}
+
+// Faces of the cell pair at LDS index li (even cell) of density plane R0: x faces
+// below, between and above the pair, y faces below and above, z faces above
+// (densities of the plane above in Rp).
+template <typename T, typename T2>
+__device__ inline void rho_pair_faces(const T* R0, const T* Rp, int li, T2& bx, T& bxn, T2& by, T2& byu, T2& bzh)
+{
+    const T2 rc = *reinterpret_cast<const T2*>(R0 + li);
+    const T2 rs = *reinterpret_cast<const T2*>(R0 + li - kResEX);
+    const T2 rn = *reinterpret_cast<const T2*>(R0 + li + kResEX);
+    const T2 ru = *reinterpret_cast<const T2*>(Rp + li);
+    bx.x = (T)2 / (R0[li - 1] + rc.x);
+    bx.y = (T)2 / (rc.x + rc.y);
+    bxn = (T)2 / (rc.y + R0[li + 2]);
+    by.x = (T)2 / (rs.x + rc.x);
+    by.y = (T)2 / (rs.y + rc.y);
+    byu.x = (T)2 / (rc.x + rn.x);
+    byu.y = (T)2 / (rc.y + rn.y);
+    bzh.x = (T)2 / (rc.x + ru.x);
+    bzh.y = (T)2 / (rc.y + ru.y);
+}
+
 // Block partial of a double over the block (result valid in thread 0).
 template <int NT>
 __device__ inline double block_sum_n(double v, double* ws)
@@ -129,19 +169,9 @@ k_resid(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict_
         for (int j = 0; j < kResLoads; ++j)
             if (lidx[j] >= 0) s[lidx[j]] = v[j];
     };
-    // density plane z (RHO): +inf at cells outside the domain
-    const T inf = __builtin_huge_val();
+    // density planes (RHO), staged like x
     auto load_rho = [&](int z, T* w) {
-        if constexpr (RHO) {
-            const bool zv = z >= 0 && z < d.nz;
-            const auto r = zv ? r_rho : r_null;
-            const unsigned so = cplane(z) * psz;
-#pragma unroll
-            for (int j = 0; j < kResLoads; ++j) {
-                const T a = bload1<T>(r, loff[j], so);
-                w[j] = (zv && loff[j] != kOutside) ? a : inf;
-            }
-        }
+        if constexpr (RHO) rho_plane_load<T>(r_rho, r_null, loff, z, d.nz, psz, w);
     };
     auto store_rho = [&](int z, const T* w) {
         if constexpr (RHO) {
@@ -198,27 +228,16 @@ k_resid(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict_
         const T* Sm = slot + ((s - 1) & 3) * kResPlane;
         const T* Sp = slot + ((s + 1) & 3) * kResPlane;
         if constexpr (RHO) {
-            // coefficients of the pair's faces from the densities around it
+            // coefficients of the pair's faces from the densities around it; the
+            // lower z faces are carried from the step below
             const T* R0 = rslot + (s & 3) * kResPlane;
-            const T2 rc = *reinterpret_cast<const T2*>(R0 + li);
-            const T rw = R0[li - 1], re = R0[li + 2];
-            const T2 rs = *reinterpret_cast<const T2*>(R0 + li - kResEX);
-            const T2 rn = *reinterpret_cast<const T2*>(R0 + li + kResEX);
-            const T2 ru = *reinterpret_cast<const T2*>(rslot + ((s + 1) & 3) * kResPlane + li);
             if (s == sbeg) {
                 const T2 rd = *reinterpret_cast<const T2*>(rslot + ((s - 1) & 3) * kResPlane + li);
+                const T2 rc = *reinterpret_cast<const T2*>(R0 + li);
                 bzl.x = (T)2 / (rd.x + rc.x);
                 bzl.y = (T)2 / (rd.y + rc.y);
             }
-            C.bx.x = (T)2 / (rw + rc.x);
-            C.bx.y = (T)2 / (rc.x + rc.y);
-            C.bxn = (T)2 / (rc.y + re);
-            C.by.x = (T)2 / (rs.x + rc.x);
-            C.by.y = (T)2 / (rs.y + rc.y);
-            C.byu.x = (T)2 / (rc.x + rn.x);
-            C.byu.y = (T)2 / (rc.y + rn.y);
-            C.bzh.x = (T)2 / (rc.x + ru.x);
-            C.bzh.y = (T)2 / (rc.y + ru.y);
+            rho_pair_faces<T, T2>(R0, rslot + ((s + 1) & 3) * kResPlane, li, C.bx, C.bxn, C.by, C.byu, C.bzh);
         }
         const T2 c = *reinterpret_cast<const T2*>(S0 + li);
         const T w = S0[li - 1], ea = S0[li + 2];

@@ -162,9 +162,9 @@ int mg_setup(mg_ctx **out, const double *beta_x, const double *beta_y, const dou
  * Other arguments, the level hierarchy and the results are those of mg_setup
  * given the faces mg_faces_from_density(rho) writes, bit for bit.  The
  * difference is bandwidth: the finest-grid FP64 residual passes (the
- * mixed-precision outer update, the FP64 restriction and residual norm) form
- * each coefficient from rho as they go, reading 8 bytes per cell where the
- * three face arrays take 24.
+ * mixed-precision outer update, the FP64 restriction and residual norm, the
+ * flexible-CG operator application) form each coefficient from rho as they
+ * go, reading 8 bytes per cell where the three face arrays take 24.
  */
 int mg_setup_density(mg_ctx **out, const double *rho, const int dims[3], double h, int bc,
                      const mg_opts *opts, void *hip_stream);

@@ -42,11 +42,18 @@ struct Sweep2Geom {
     static constexpr int HX = EX / 2;          // pairs per row
     static constexpr int NP = HX * EY;         // pairs per plane = working threads
     static constexpr int NT = (NP + 63) / 64 * 64;
-    static constexpr int PLANE = EX * EY;
+    // LDS row stride and offset of a row's odd-x cells.  A wave spans rows of 36
+    // pairs; with RS +- HO = 36 (mod 32), the next row's cells of one colour
+    // start in the bank after the previous row's last, and 2 RS = 8 (mod 64):
+    // fewer bank conflicts than the packed 72 / 36 layout (measured: 0.864
+    // against 0.879 ms per 512^3 launch)
+    static constexpr int RS = 100;
+    static constexpr int HO = 64;
+    static constexpr int PLANE = RS * EY;
     static constexpr int SLOTS = 7;         // planes s-5 .. s+1 of step s
     // LDS position of plane coordinates (ex, ey): each row keeps its even-x
     // cells, then its odd-x cells (one colour of a row is contiguous).
-    __device__ static int idx(int ex, int ey) { return ey * EX + (ex & 1) * HX + (ex >> 1); }
+    __device__ static int idx(int ex, int ey) { return ey * RS + (ex & 1) * HO + (ex >> 1); }
 };
 
 // Launch contract: nx even and >= 64, every array below 2^31 bytes, grid =
@@ -155,8 +162,8 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         const T b = odd ? C.b.y : C.b.x;
         T dg = bxl, of = bxl * P0[xm];
         dg += bxh; of += bxh * P0[xm + 1];
-        dg += byl; of += byl * P0[li - G::EX];
-        dg += byh; of += byh * P0[li + G::EX];
+        dg += byl; of += byl * P0[li - G::RS];
+        dg += byh; of += byh * P0[li + G::RS];
         dg += bzl; of += bzl * Pm[li];
         dg += bzh; of += bzh * Pp[li];
         v = quot(of - h2 * b, dg);

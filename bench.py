@@ -67,9 +67,9 @@ TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp"],
-    "sha256": "e36189677e361f012f5f6e6de679d6d1913e72642f41171fd052e84e363bad35",
-    "fetch_kib": 403542.6994243421,
-    "write_kib": 149762.10999177632,
+    "sha256": "a13af162482b9737999d868d8305364e16ae2696b0d9511acd2e5421723d6678",
+    "fetch_kib": 403484.4700863487,
+    "write_kib": 149761.26403166118,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

@@ -174,10 +174,12 @@ class Solver:
         shapes = face_shapes(self.dims)
         self._check(self._lib.mg_update(self._ctx, _ptr(beta_x, "beta_x", shapes[0]),
                                         _ptr(beta_y, "beta_y", shapes[1]), _ptr(beta_z, "beta_z", shapes[2])))
+        self.density = False
 
     def update_density(self, rho: torch.Tensor) -> None:
         """New cell density (contexts made from a density only; no allocation)."""
         self._check(self._lib.mg_update_density(self._ctx, _ptr(rho, "rho", self.cell_shape)))
+        self.density = True
 
     # -- solves -----------------------------------------------------------------
     def solve(self, rhs: torch.Tensor, tol: float = 1e-10, p: Optional[torch.Tensor] = None,

@@ -67,9 +67,9 @@ TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp"],
-    "sha256": "a13af162482b9737999d868d8305364e16ae2696b0d9511acd2e5421723d6678",
-    "fetch_kib": 403484.4700863487,
-    "write_kib": 149761.26403166118,
+    "sha256": "420e56d7d4471f15b4378c310294873f329d1292f409348ed1d43f318d898e02",
+    "fetch_kib": 404011.8806573276,
+    "write_kib": 149760.9647090517,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
@@ -274,6 +274,9 @@ def main() -> int:
 
     stream = torch.cuda.current_stream()
     mixed = make(precision="mixed", zero_guess=True, timing=True)
+    # inside the timed steps only the dominant kernel (the two-sweep smoother) carries
+    # timing events: each timed launch costs the GPU a few microseconds before it
+    mixed.set_timing_classes([S.L.MG_K_SWEEP2])
     p = torch.zeros_like(rhs)
     lam = torch.zeros_like(rhs)
 
@@ -315,7 +318,15 @@ def main() -> int:
     mixed_cycles = solve_stats[-1].cycles
     mixed_rr = max(s.rel_res for s in solve_stats)
     ksum = kernel_summary(solve_stats + [r[2] for r in recs], "mixed", coef)
-    dominant = max(ksum, key=lambda k: ksum[k]["ms_total"]) if ksum else None
+    # every class, from one more forward + adjoint solve with all launches timed
+    mixed.set_timing_classes(None)
+    _, st_all = mixed.solve(rhs, args.tol, p=p)
+    _, sta_all = mixed.solve_adjoint(w, args.tol, lam=lam)
+    torch.cuda.synchronize()
+    ksum_all = kernel_summary([st_all, sta_all], "mixed", coef)
+    dominant = max(ksum_all, key=lambda k: ksum_all[k]["ms_total"]) if ksum_all else None
+    if dominant not in ksum:
+        raise RuntimeError(f"dominant kernel class {dominant} was not timed inside the timed steps")
     setup_ms = solve_stats[-1].setup_ms
     err_vs_oracle = sampled_error_vs_oracle(p, n, args.drops, args.tol)
     copy_gbps = measure_copy_gbps(stream)
@@ -424,7 +435,11 @@ def main() -> int:
         "mixed": {"time_to_tol_ms": mixed_ms, "cycles": mixed_cycles, "rel_res_max": mixed_rr,
                   "setup_ms": setup_ms, "error_vs_oracle": err_vs_oracle,
                   **smoother_figures(ksum, cells),
-                  "kernels": ksum},
+                  "kernels_timed_steps": ksum,
+                  "kernels": ksum_all,
+                  "kernels_note": "kernels_timed_steps: HIP events on every launch of the dominant kernel "
+                                  "inside the timed steps (the roofline); kernels: every class, from one "
+                                  "more forward + adjoint solve after them with all launches timed"},
         "mixed_from_faces": mixed_faces,
         "fp64": fp64,
         "fcg": fcg,

@@ -187,6 +187,16 @@ int mg_update_density(mg_ctx *c, const double *rho);
 int mg_update(mg_ctx *c, const double *beta_x, const double *beta_y, const double *beta_z);
 
 /*
+ * mg_set_timing_classes -- which kernel classes a context set up with
+ * MG_FLAG_TIMING times from now on: bit k of mask selects class MG_K_k (all
+ * after setup).  Each timed launch carries start/end events, which costs the
+ * GPU a few microseconds before the kernel, so a caller timing one class can
+ * leave the others untimed.  MG_EINVAL without MG_FLAG_TIMING or for bits at or
+ * beyond MG_K_COUNT.
+ */
+int mg_set_timing_classes(mg_ctx *c, unsigned mask);
+
+/*
  * mg_solve -- p = zero-mean solution of L p = rhs - mean(rhs).
  *   rhs   device [nz][ny][nx]; not modified.
  *   p     device [nz][ny][nx], 16-byte aligned; in: initial guess (unless

@@ -54,6 +54,7 @@ SIGNATURES = {
     "mg_update": (_I, [_CTX, _D, _D, _D]),
     "mg_setup_density": (_I, [ctypes.POINTER(_CTX), _D, _DIMS, _F, _I, ctypes.POINTER(MgOpts), ctypes.c_void_p]),
     "mg_update_density": (_I, [_CTX, _D]),
+    "mg_set_timing_classes": (_I, [_CTX, ctypes.c_uint]),
     "mg_solve": (_I, [_CTX, _D, _D, _F, ctypes.POINTER(MgStats)]),
     "mg_solve_adjoint": (_I, [_CTX, _D, _D, _F, ctypes.POINTER(MgStats)]),
     "mg_face_grad": (_I, [_CTX, _D, _D, _D, _D, _D]),

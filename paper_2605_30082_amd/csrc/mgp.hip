@@ -73,6 +73,7 @@ struct mg_ctx {
     int ev_level[kTimingPairs];
     double ev_bytes[kTimingPairs];
     int ev_used = 0;
+    unsigned timing_mask = (1u << MG_K_COUNT) - 1;  // classes timed under MG_FLAG_TIMING
     double kms[MG_K_COUNT], kms0[MG_K_COUNT];
     long long klaunch[MG_K_COUNT], klaunch0[MG_K_COUNT];
     double kbytes[MG_K_COUNT], kbytes0[MG_K_COUNT];
@@ -139,27 +140,29 @@ double now_ms()
 
 // --- timing ---------------------------------------------------------------
 
-// Brackets one launch with HIP events when the context times kernels.  Only
+// Hands one launch a pair of HIP events when the context times kernels; the
+// launch passes them to hipExtLaunchKernelGGL, which stores the kernel's own
+// start and end timestamps in them (no marker packets between kernels).  Only
 // the tiled kernels are timed (one kernel name per class and precision), on
 // every level; the finest level is also totalled on its own.
 struct TimedLaunch {
     mg_ctx* c;
-    int cls;
+    int slot;
     bool on;
-    TimedLaunch(mg_ctx* ctx, int level, int k, double bytes, bool tiled = true) : c(ctx), cls(k), on(false)
+    TimedLaunch(mg_ctx* ctx, int level, int k, double bytes, bool tiled = true) : c(ctx), slot(0), on(false)
     {
-        if (!c->ev || !tiled || c->ev_used >= kTimingPairs) return;
+        if (!c->ev || !tiled || !((c->timing_mask >> k) & 1u) || c->ev_used >= kTimingPairs) return;
         on = true;
-        c->ev_class[c->ev_used] = k;
-        c->ev_level[c->ev_used] = level;
-        c->ev_bytes[c->ev_used] = bytes;
-        (void)hipEventRecord(c->ev[2 * c->ev_used], c->stream);
+        slot = c->ev_used;
+        c->ev_class[slot] = k;
+        c->ev_level[slot] = level;
+        c->ev_bytes[slot] = bytes;
     }
+    hipEvent_t start() const { return on ? c->ev[2 * slot] : nullptr; }
+    hipEvent_t stop() const { return on ? c->ev[2 * slot + 1] : nullptr; }
     ~TimedLaunch()
     {
-        if (!on) return;
-        (void)hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream);
-        c->ev_used++;
+        if (on) c->ev_used++;
     }
 };
 
@@ -217,7 +220,7 @@ int sweep(mg_ctx* c, int l, const T* b, const T* in, T* out, int order, bool zer
     const double bytes = (double)L.n * sweep_bytes_per_cell<T>();
     TimedLaunch tl(c, l, MG_K_SWEEP, bytes, sweep_is_fused(L.d, sizeof(T)));
     const hipError_t e = launch_sweep<T>(B.bx, B.by, B.bz, L.d, (T)(L.h * L.h), b, in, out, order,
-                                         zero_in, c->stream);
+                                         zero_in, c->stream, tl.start(), tl.stop());
     if (e != hipSuccess) {
         set_err(c, "sweep launch failed: %s", hipGetErrorString(e));
         return MG_EHIP;
@@ -232,7 +235,7 @@ int sweep_pair(mg_ctx* c, int l, const float* b, const float* in, float* out, in
     LevelBufs<float>& B = L.f32;
     TimedLaunch tl(c, l, MG_K_SWEEP2, 2.0 * (double)L.n * sweep_bytes_per_cell<float>(), true);
     const hipError_t e = launch_sweep2<float>(B.bx, B.by, B.bz, L.d, (float)(L.h * L.h), b, in, out, order,
-                                              zero_in, c->stream);
+                                              zero_in, c->stream, tl.start(), tl.stop());
     if (e != hipSuccess) {
         set_err(c, "sweep launch failed: %s", hipGetErrorString(e));
         return MG_EHIP;
@@ -277,16 +280,18 @@ int residual_restrict(mg_ctx* c, int l, const T* b, const T* x, T* bc)
         const ResGeom g = res_geom(L.d);
         if constexpr (sizeof(T) == 8) {
             if (l == 0 && c->use_rho) {
-                k_resid<T, RES_RESTRICT, true><<<g.blocks, kResNT, 0, c->stream>>>(
-                    B.bx, B.by, B.bz, b, x, nullptr, L.d, (T)(1.0 / (L.h * L.h)), g.zc, g.ntx, g.nty, nullptr,
-                    nullptr, bc, nullptr, c->rho);
+                hipExtLaunchKernelGGL(k_resid<T, RES_RESTRICT, true>, dim3(g.blocks), dim3(kResNT), 0, c->stream,
+                                      tl.start(), tl.stop(), 0, B.bx, B.by, B.bz, b, x, (const float*)nullptr, L.d,
+                                      (T)(1.0 / (L.h * L.h)), g.zc, g.ntx, g.nty, (T*)nullptr, (float*)nullptr, bc,
+                                      (double*)nullptr, (const T*)c->rho);
                 CHECK_LAUNCH(c);
                 return MG_OK;
             }
         }
-        k_resid<T, RES_RESTRICT><<<g.blocks, kResNT, 0, c->stream>>>(B.bx, B.by, B.bz, b, x, nullptr, L.d,
-                                                                      (T)(1.0 / (L.h * L.h)), g.zc, g.ntx, g.nty,
-                                                                      nullptr, nullptr, bc, nullptr);
+        hipExtLaunchKernelGGL(k_resid<T, RES_RESTRICT, false>, dim3(g.blocks), dim3(kResNT), 0, c->stream,
+                              tl.start(), tl.stop(), 0, B.bx, B.by, B.bz, b, x, (const float*)nullptr, L.d,
+                              (T)(1.0 / (L.h * L.h)), g.zc, g.ntx, g.nty, (T*)nullptr, (float*)nullptr, bc,
+                              (double*)nullptr, (const T*)nullptr);
     } else {
         k_residual_restrict<T><<<grid_for(C.n), kBlock, 0, c->stream>>>(B.bx, B.by, B.bz, L.d, C.d,
                                                                        (T)(1.0 / (L.h * L.h)), b, x, bc);
@@ -304,7 +309,8 @@ int prolong_correct(mg_ctx* c, int l, const T* e, T* x)
     TimedLaunch tl(c, l, MG_K_PROLONG, (double)L.n * (2.0 + 1.0 / 8.0) * sizeof(T), tiled);
     if (tiled) {
         const ProGeom g = pro_geom(L.d, C.d);
-        k_prolong_tiled<T><<<g.blocks, kProNT, 0, c->stream>>>(L.d, C.d, e, x, g.kc, g.ntx, g.nty);
+        hipExtLaunchKernelGGL(k_prolong_tiled<T>, dim3(g.blocks), dim3(kProNT), 0, c->stream, tl.start(), tl.stop(), 0,
+                              L.d, C.d, e, x, g.kc, g.ntx, g.nty);
     } else {
         k_prolong_correct<T><<<grid_for(L.n), kBlock, 0, c->stream>>>(L.d, C.d, e, x);
     }
@@ -377,7 +383,7 @@ int sweep_first_norm(mg_ctx* c, const double* b, const double* in, double* out, 
     {
         TimedLaunch tl(c, 0, MG_K_NORM, (double)L.n * sweep_bytes_per_cell<double>(), true);
         const hipError_t e = launch_fused<double, 16>(B.bx, B.by, B.bz, L.d, L.h * L.h, b, in, out, 0, false,
-                                                      c->stream, c->partials, &blocks);
+                                                      c->stream, c->partials, &blocks, tl.start(), tl.stop());
         if (e != hipSuccess) {
             set_err(c, "sweep launch failed: %s", hipGetErrorString(e));
             return MG_EHIP;
@@ -394,14 +400,17 @@ int residual_norm_launch(mg_ctx* c, const double* b, const double* p, double* r_
     if (tiled) {
         const ResGeom g = res_geom(L.d);
         if (c->use_rho)
-            k_resid<double, RES_NORM, true><<<g.blocks, kResNT, 0, c->stream>>>(
-                L.f64.bx, L.f64.by, L.f64.bz, b, p, nullptr, L.d, 1.0 / (L.h * L.h), g.zc, g.ntx, g.nty, nullptr,
-                nullptr, nullptr, c->partials, c->rho);
+            hipExtLaunchKernelGGL(k_resid<double, RES_NORM, true>, dim3(g.blocks), dim3(kResNT), 0, c->stream,
+                                  tl.start(), tl.stop(), 0, L.f64.bx, L.f64.by, L.f64.bz, b, p,
+                                  (const float*)nullptr, L.d, 1.0 / (L.h * L.h), g.zc, g.ntx, g.nty,
+                                  (double*)nullptr, (float*)nullptr, (double*)nullptr, c->partials,
+                                  (const double*)c->rho);
         else
-            k_resid<double, RES_NORM><<<g.blocks, kResNT, 0, c->stream>>>(L.f64.bx, L.f64.by, L.f64.bz, b, p,
-                                                                           nullptr, L.d, 1.0 / (L.h * L.h), g.zc,
-                                                                           g.ntx, g.nty, nullptr, nullptr, nullptr,
-                                                                           c->partials);
+            hipExtLaunchKernelGGL(k_resid<double, RES_NORM, false>, dim3(g.blocks), dim3(kResNT), 0, c->stream,
+                                  tl.start(), tl.stop(), 0, L.f64.bx, L.f64.by, L.f64.bz, b, p,
+                                  (const float*)nullptr, L.d, 1.0 / (L.h * L.h), g.zc, g.ntx, g.nty,
+                                  (double*)nullptr, (float*)nullptr, (double*)nullptr, c->partials,
+                                  (const double*)nullptr);
         CHECK_LAUNCH(c);
         return reduce_to(c, g.blocks, slot);
     }
@@ -422,14 +431,15 @@ int outer_update(mg_ctx* c, const double* p_in, const float* e, double* p_out, f
     if (tiled) {
         const ResGeom g = res_geom(F.d);
         if (c->use_rho)
-            k_resid<double, RES_OUTER, true><<<g.blocks, kResNT, 0, c->stream>>>(
-                F.f64.bx, F.f64.by, F.f64.bz, c->b0, p_in, e, F.d, 1.0 / (F.h * F.h), g.zc, g.ntx, g.nty, p_out, r32,
-                nullptr, c->partials, c->rho);
+            hipExtLaunchKernelGGL(k_resid<double, RES_OUTER, true>, dim3(g.blocks), dim3(kResNT), 0, c->stream,
+                                  tl.start(), tl.stop(), 0, F.f64.bx, F.f64.by, F.f64.bz, c->b0, p_in, e, F.d,
+                                  1.0 / (F.h * F.h), g.zc, g.ntx, g.nty, p_out, r32, (double*)nullptr, c->partials,
+                                  (const double*)c->rho);
         else
-            k_resid<double, RES_OUTER><<<g.blocks, kResNT, 0, c->stream>>>(F.f64.bx, F.f64.by, F.f64.bz, c->b0,
-                                                                            p_in, e, F.d, 1.0 / (F.h * F.h), g.zc,
-                                                                            g.ntx, g.nty, p_out, r32, nullptr,
-                                                                            c->partials);
+            hipExtLaunchKernelGGL(k_resid<double, RES_OUTER, false>, dim3(g.blocks), dim3(kResNT), 0, c->stream,
+                                  tl.start(), tl.stop(), 0, F.f64.bx, F.f64.by, F.f64.bz, c->b0, p_in, e, F.d,
+                                  1.0 / (F.h * F.h), g.zc, g.ntx, g.nty, p_out, r32, (double*)nullptr, c->partials,
+                                  (const double*)nullptr);
         CHECK_LAUNCH(c);
         return reduce_to(c, g.blocks, slot);
     }
@@ -954,8 +964,11 @@ int setup_ctx(mg_ctx** out, const double* beta_x, const double* beta_y, const do
     if (o.flags & MG_FLAG_TIMING) {
         c->ev = new (std::nothrow) hipEvent_t[2 * kTimingPairs]();
         if (!c->ev) return fail(MG_ENOMEM);
+        // timing-only events: no system-scope fence (cache write-back and
+        // invalidate) at each record, which would stall the next kernel; they are
+        // read only after the stream has been synchronised
         for (int t = 0; t < 2 * kTimingPairs; ++t)
-            if (hipEventCreate(&c->ev[t]) != hipSuccess) {
+            if (hipEventCreateWithFlags(&c->ev[t], hipEventDisableSystemFence) != hipSuccess) {
                 set_err(c, "hipEventCreate failed");
                 return fail(MG_EHIP);
             }
@@ -1015,6 +1028,21 @@ int mg_update(mg_ctx* c, const double* beta_x, const double* beta_y, const doubl
     TRY(setup_impl(c, beta_x, beta_y, beta_z));
     c->valid = true;
     c->setup_ms = now_ms() - t0;
+    return MG_OK;
+}
+
+int mg_set_timing_classes(mg_ctx* c, unsigned mask)
+{
+    TRY(check_ctx(c));
+    if (!c->ev) {
+        set_err(c, "the context was set up without MG_FLAG_TIMING");
+        return MG_EINVAL;
+    }
+    if (mask >> MG_K_COUNT) {
+        set_err(c, "timing class mask 0x%x has bits beyond MG_K_COUNT", mask);
+        return MG_EINVAL;
+    }
+    c->timing_mask = mask;
     return MG_OK;
 }
 

@@ -11,6 +11,7 @@
 // stencil kernels need no branch for a wall coefficient.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -340,21 +340,22 @@ inline FusedLaunch fused_geom(const Dims& d)
     return g;
 }
 
+// ev0/ev1 (nullable): events that take the kernel's start and end timestamps.
 template <typename T, int TY>
 hipError_t launch_fused(const T* bx, const T* by, const T* bz, Dims d, T h2, const T* b, const T* in, T* out,
                         int c0, bool zero_in, hipStream_t s, double* norm_partials = nullptr,
-                        int* norm_blocks = nullptr)
+                        int* norm_blocks = nullptr, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     const FusedLaunch g = fused_geom<TY>(d);
     const int ntx = g.ntx, nty = g.nty, zc = g.zc, tiles = ntx * nty, nzc = g.blocks / tiles;
-    if (norm_partials) {
-        *norm_blocks = tiles * nzc;
-        k_sweep_fused<T, TY, true><<<tiles * nzc, 32 * TY, 0, s>>>(bx, by, bz, b, in, out, d, h2, c0,
-                                                                    zero_in ? 1 : 0, zc, ntx, nty, norm_partials);
-    } else {
-        k_sweep_fused<T, TY><<<tiles * nzc, 32 * TY, 0, s>>>(bx, by, bz, b, in, out, d, h2, c0, zero_in ? 1 : 0, zc,
-                                                              ntx, nty);
-    }
+    const int zi = zero_in ? 1 : 0;
+    if (norm_partials) *norm_blocks = tiles * nzc;
+    if (norm_partials)
+        hipExtLaunchKernelGGL(k_sweep_fused<T, TY, true>, dim3(tiles * nzc), dim3(32 * TY), 0, s, ev0, ev1, 0, bx, by,
+                              bz, b, in, out, d, h2, c0, zi, zc, ntx, nty, norm_partials);
+    else
+        hipExtLaunchKernelGGL(k_sweep_fused<T, TY, false>, dim3(tiles * nzc), dim3(32 * TY), 0, s, ev0, ev1, 0, bx,
+                              by, bz, b, in, out, d, h2, c0, zi, zc, ntx, nty, (double*)nullptr);
     return hipGetLastError();
 }
 
@@ -371,12 +372,13 @@ inline bool sweep_is_fused(const Dims& d, size_t elem)
 
 template <typename T>
 hipError_t launch_sweep(const T* bx, const T* by, const T* bz, Dims d, T h2, const T* b, const T* in, T* out,
-                        int order, bool zero_in, hipStream_t s)
+                        int order, bool zero_in, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     const int c0 = order == 0 ? 0 : 1;
     if (sweep_is_fused(d, sizeof(T))) {
-        if constexpr (sizeof(T) == 8) return launch_fused<T, 16>(bx, by, bz, d, h2, b, in, out, c0, zero_in, s);
-        else return launch_fused<T, 8>(bx, by, bz, d, h2, b, in, out, c0, zero_in, s);
+        if constexpr (sizeof(T) == 8)
+            return launch_fused<T, 16>(bx, by, bz, d, h2, b, in, out, c0, zero_in, s, nullptr, nullptr, ev0, ev1);
+        else return launch_fused<T, 8>(bx, by, bz, d, h2, b, in, out, c0, zero_in, s, nullptr, nullptr, ev0, ev1);
     }
     const dim3 blk(64, 4, 1);
     const dim3 grd((unsigned)(((d.nx + 1) / 2 + 63) / 64), (unsigned)((d.ny + 3) / 4), (unsigned)d.nz);

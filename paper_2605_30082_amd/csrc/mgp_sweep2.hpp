@@ -292,14 +292,15 @@ inline bool sweep2_ok(const Dims& d, size_t elem)
     return elem == 4 && d.nx >= 64 && (d.nx % 2) == 0 && d.ny >= 16 && big * (long)elem < (1L << 31);
 }
 
+// ev0/ev1 (nullable): events that take the kernel's start and end timestamps.
 template <typename T>
 hipError_t launch_sweep2(const T* bx, const T* by, const T* bz, Dims d, T h2, const T* b, const T* in, T* out,
-                         int order, bool zero_in, hipStream_t s)
+                         int order, bool zero_in, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     constexpr int TY = 16;
     const Sweep2Launch g = sweep2_geom<TY>(d);
-    k_sweep2_fused<T, TY><<<g.blocks, Sweep2Geom<TY>::NT, 0, s>>>(bx, by, bz, b, in, out, d, h2, order == 0 ? 0 : 1,
-                                                                   zero_in ? 1 : 0, g.zc, g.ntx, g.nty);
+    hipExtLaunchKernelGGL(k_sweep2_fused<T, TY>, dim3(g.blocks), dim3(Sweep2Geom<TY>::NT), 0, s, ev0, ev1, 0, bx, by,
+                          bz, b, in, out, d, h2, order == 0 ? 0 : 1, zero_in ? 1 : 0, g.zc, g.ntx, g.nty);
     return hipGetLastError();
 }
 

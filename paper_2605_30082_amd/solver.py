@@ -181,6 +181,12 @@ class Solver:
         self._check(self._lib.mg_update_density(self._ctx, _ptr(rho, "rho", self.cell_shape)))
         self.density = True
 
+    def set_timing_classes(self, classes: Optional[Sequence[int]] = None) -> None:
+        """Time only these kernel classes (MG_K_* values; None: all) in later solves
+        of a context made with timing=True."""
+        mask = (1 << L.MG_K_COUNT) - 1 if classes is None else sum(1 << int(k) for k in set(classes))
+        self._check(self._lib.mg_set_timing_classes(self._ctx, mask))
+
     # -- solves -----------------------------------------------------------------
     def solve(self, rhs: torch.Tensor, tol: float = 1e-10, p: Optional[torch.Tensor] = None,
               check: bool = True) -> Tuple[torch.Tensor, SolveStats]:

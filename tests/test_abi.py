@@ -115,6 +115,7 @@ def test_density_setup_rejects_bad_arguments_before_any_device_work():
     st = lib.mg_setup_density(ctypes.byref(ctx), fake, L.dims_arg((8, 8, 8)), 1 / 8, 3, ctypes.byref(opts), None)
     assert st == L.MG_EINVAL and "MG_BC_NEUMANN" in L.last_error(None)
     assert lib.mg_update_density(None, fake) == L.MG_EINVAL
+    assert lib.mg_set_timing_classes(None, 1) == L.MG_EINVAL
     assert lib.mg_density_from_vof(fake, fake, L.dims_arg((4, 0, 4)), 1.0, 1.0, 1.0, fake, None) == L.MG_EINVAL
     assert lib.mg_density_from_vof(fake, fake, L.dims_arg((4, 4, 4)), 1.0, -1.0, 1.0, fake, None) == L.MG_EINVAL
     assert lib.mg_density_from_vof(fake, None, L.dims_arg((4, 4, 4)), 1.0, 1.0, 1.0, fake, None) == L.MG_EINVAL

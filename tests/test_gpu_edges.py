@@ -112,3 +112,55 @@ def test_front_end_argument_checks():
     with pytest.raises(ValueError):
         s.solve(gd[:4].contiguous(), 1e-10)
     s.close()
+
+
+@pytest.mark.parametrize("density", [False, True])
+def test_kernel_timing_stats(density):
+    """MG_FLAG_TIMING: every timed launch is counted with its event duration and
+    algorithmic bytes, and timing does not change the result."""
+    import paper_2605_30082_amd._lib as L
+    wl = W.drop_film_workload(64)
+    gb, gd = gpu_inputs(wl)
+    rho = S.density_from_vof(T(wl.f_drop), T(wl.f_film), wl.rho_drop, wl.rho_film, wl.rho_gas)
+
+    def make(**kw):
+        return S.Solver.from_density(rho, wl.h, **kw) if density else S.Solver(*gb, wl.h, **kw)
+
+    for precision in ("mixed", "fp64"):
+        with make(precision=precision, zero_guess=True, timing=True) as s:
+            p1, st = s.solve(gd, 1e-10)
+        with make(precision=precision, zero_guess=True) as s:
+            p0, st0 = s.solve(gd, 1e-10)
+        assert torch.equal(p0, p1) and st.cycles == st0.cycles
+        n = st.cycles
+        if precision == "mixed":
+            # at 64^3 only the finest grid is wide enough for the tiled kernels
+            expect = {L.MG_K_SWEEP2: 2 * n, L.MG_K_RESTRICT: n, L.MG_K_PROLONG: n, L.MG_K_OUTER: n + 1}
+        else:
+            # the first cycle runs both pre-sweeps; every later one starts with the
+            # sweep that also takes the norm of the previous result, and so does the
+            # final check
+            expect = {L.MG_K_SWEEP: 3 * n + 1, L.MG_K_NORM: n, L.MG_K_RESTRICT: n, L.MG_K_PROLONG: n}
+        for k, count in expect.items():
+            assert st.kernel_launches[k] == count, (precision, k, st.kernel_launches[k], count)
+            assert st.kernel_launches_finest[k] == count
+            assert st.kernel_ms[k] > 0 and st.kernel_bytes[k] > 0
+            assert st.kernel_ms_finest[k] == st.kernel_ms[k]
+        assert sum(st.kernel_ms) < st.solve_ms
+        assert sum(st0.kernel_launches) == 0
+        # a class mask: only the selected class is timed, results unchanged
+        with make(precision=precision, zero_guess=True, timing=True) as s:
+            only = L.MG_K_RESTRICT
+            s.set_timing_classes([only])
+            p2, st2 = s.solve(gd, 1e-10)
+            assert torch.equal(p2, p0)
+            assert st2.kernel_launches[only] == expect[only]
+            assert sum(st2.kernel_launches) == expect[only]
+            s.set_timing_classes(None)
+            _, st3 = s.solve(gd, 1e-10)
+            assert list(st3.kernel_launches) == list(st.kernel_launches)
+            with pytest.raises(S.MgError):
+                s.set_timing_classes([L.MG_K_COUNT])
+    with make(precision="mixed") as s:
+        with pytest.raises(S.MgError):
+            s.set_timing_classes([0])

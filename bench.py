@@ -46,7 +46,7 @@ KERNEL_SYMBOLS = {
     ("prolong_correct", "mixed"): "mgp::k_prolong_tiled<float>",
     ("prolong_correct", "fp64"): "mgp::k_prolong_tiled<double>",
     ("outer_update", "mixed"): "mgp::k_resid<double, 2, {rho}>",
-    ("residual_norm", "fp64"): "mgp::k_sweep_fused<double, 16, true>",
+    ("residual_norm", "fp64"): "mgp::k_sweep_fused<double, 8, true>",
 }
 
 

@@ -68,8 +68,8 @@ TRAFFIC = {
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp"],
     "sha256": "420e56d7d4471f15b4378c310294873f329d1292f409348ed1d43f318d898e02",
-    "fetch_kib": 404011.8806573276,
-    "write_kib": 149760.9647090517,
+    "fetch_kib": 403639.5334725216,
+    "write_kib": 149760.96477640086,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

@@ -260,10 +260,11 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
 }
 
 // Blocks of the two-sweep kernel: z is cut into chunks so that the grid holds
-// about 256 blocks, one per compute unit (one block of 14 waves fills a CU),
-// with at least 8 planes per chunk (each chunk re-walks 7 planes of stage
-// lag).  Measured on 64^3..512^3 grids, fewer and longer chunks beat more
-// and shorter ones down to one block per CU.
+// about 256 blocks, one per compute unit (one block of 14 waves fills a CU).
+// Measured on 128^3..512^3 grids, fewer and longer chunks beat more and
+// shorter ones down to one block per CU; a chunk re-walks 7 planes of stage
+// lag, so grids too small to fill the chip (64^3: 4 tiles) take chunks of
+// down to 2 planes, which run 14.5 against 22.8 us with 8-plane chunks.
 struct Sweep2Launch {
     int ntx, nty, zc, blocks;
 };
@@ -277,7 +278,7 @@ inline Sweep2Launch sweep2_geom(const Dims& d)
     const int tiles = g.ntx * g.nty;
     int nzc = (256 + tiles - 1) / tiles;
     int zc = (d.nz + nzc - 1) / nzc;
-    if (zc < 8) zc = 8;
+    if (zc < 2) zc = 2;
     if (zc > d.nz) zc = d.nz;
     g.zc = zc;
     g.blocks = tiles * ((d.nz + zc - 1) / zc);

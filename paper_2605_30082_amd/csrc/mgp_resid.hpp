@@ -306,7 +306,12 @@ inline ResGeom res_geom(const Dims& d)
     const int tiles = g.ntx * g.nty;
     int nzc = (2048 + tiles - 1) / tiles;
     int zc = (d.nz + nzc - 1) / nzc;
-    if (zc < 8) zc = 8;
+    // at least 8 planes (each chunk re-reads two planes and restarts its
+    // pipeline) unless that leaves fewer than 1024 blocks: small grids take
+    // chunks of 2 (at 64^3 / 128^3: 5.9 / 10.0 against 13.5 / 13.6 us)
+    const int z8 = zc < 8 ? 8 : zc;
+    if ((long)tiles * ((d.nz + z8 - 1) / z8) >= 1024) zc = z8;
+    if (zc < 2) zc = 2;
     zc += zc & 1;
     if (zc >= d.nz) zc = d.nz;
     g.zc = zc;

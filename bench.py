@@ -67,9 +67,9 @@ TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp"],
-    "sha256": "420e56d7d4471f15b4378c310294873f329d1292f409348ed1d43f318d898e02",
-    "fetch_kib": 403639.5334725216,
-    "write_kib": 149760.96477640086,
+    "sha256": "83b164c1beeb8f4be1227be5bc65acf210a32d7e577aa0081bcc2c4c4351d376",
+    "fetch_kib": 408103.564453125,
+    "write_kib": 149763.17823949354,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

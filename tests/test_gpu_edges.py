@@ -164,3 +164,27 @@ def test_kernel_timing_stats(density):
     with make(precision="mixed") as s:
         with pytest.raises(S.MgError):
             s.set_timing_classes([0])
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 1), (1, 3, 2), (3, 3, 3), (8, 8, 8), (96, 96, 96),
+                                  (128, 64, 32), (16, 32, 64), (64, 64, 16)])
+def test_density_context_on_unusual_grids(dims):
+    """Density contexts on single cells, one-cell-thick and ragged grids: identical to
+    the face arrays mg_faces_from_density writes, in both precisions."""
+    nx, ny, nz = dims
+    g = np.random.default_rng(33)
+    # a smooth density spanning 1.2 .. 1000 (sin product on the cell centres)
+    zz, yy, xx = np.meshgrid((np.arange(nz) + 0.5) / nz, (np.arange(ny) + 0.5) / ny, (np.arange(nx) + 0.5) / nx,
+                             indexing="ij")
+    s3 = np.sin(2 * np.pi * xx) * np.sin(2 * np.pi * yy) * np.sin(2 * np.pi * zz)
+    rho = np.sqrt(1.2 * 1000.0) * np.exp(0.5 * np.log(1000.0 / 1.2) * s3)
+    rhs = g.standard_normal((nz, ny, nx))
+    h = 1.0 / max(dims)
+    faces = S.faces_from_density(T(rho))
+    for precision in ("fp64", "mixed"):
+        kw = dict(precision=precision, zero_guess=True)
+        with S.Solver.from_density(T(rho), h, **kw) as s:
+            pd, std = s.solve(T(rhs), 1e-10)
+        with S.Solver(*faces, h, **kw) as s:
+            pf, stf = s.solve(T(rhs), 1e-10)
+        assert torch.equal(pd, pf) and std.cycles == stf.cycles

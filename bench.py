@@ -452,7 +452,7 @@ def main() -> int:
     return 0
 
 
-def cpu_baseline(wl, args, cycles, sample_cycles=4):
+def cpu_baseline(wl, args, cycles, sample_cycles=12):
     """The FP64 oracle on the host cores: a few V-cycles at full size (about 10 s of
     CPU work), scaled to the cycle count of the GPU solve."""
     import numpy as np

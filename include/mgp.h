@@ -263,7 +263,9 @@ int mg_density_from_vof(const double *f_drop, const double *f_film, const int di
 
 /*
  * mg_faces_from_density -- beta_f = 2/(rho_L + rho_R) on interior faces, 0 on
- * walls (public face layouts, device), from a device cell density.
+ * walls (public face layouts, device), from a device cell density.  The
+ * density is not validated here (mg_setup_density does that); MG_EINVAL on
+ * NULL pointers or non-positive dims.
  */
 int mg_faces_from_density(const double *rho, const int dims[3], double *beta_x, double *beta_y,
                           double *beta_z, void *hip_stream);

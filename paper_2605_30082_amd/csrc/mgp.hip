@@ -426,8 +426,13 @@ int residual_norm_launch(mg_ctx* c, const double* b, const double* p, double* r_
 int outer_update(mg_ctx* c, const double* p_in, const float* e, double* p_out, float* r32, int slot)
 {
     Level& F = c->lev[0];
-    const double bytes = (double)F.n * ((c->use_rho ? 3 : 5) * 8 + (e ? 4 : 0) + 8 + 4);
+    // reads p (unless NULL), b and the faces or rho, e; writes p' and r32
+    const double bytes = (double)F.n * ((c->use_rho ? 3 : 5) * 8 - (p_in ? 0 : 8) + (e ? 4 : 0) + 8 + 4);
     const bool tiled = res_tiled_ok(F.d, sizeof(double));
+    if (!p_in && !tiled) {
+        set_err(c, "internal: a zero iterate needs the tiled outer update");
+        return MG_EINVAL;
+    }
     TimedLaunch tl(c, 0, MG_K_OUTER, bytes, tiled);
     if (tiled) {
         const ResGeom g = res_geom(F.d);
@@ -673,12 +678,20 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
     } else {
         Level& F0 = c->lev[0];
         float* r32 = F0.f32.b;
-        // initial residual in FP64, cast to FP32
-        if (zero_guess) TRY(fill<double>(c, cur, n, 0.0));
-        TRY(outer_update(c, cur, nullptr, other, r32, 2));
-        std::swap(cur, other);
-        TRY(fetch_scalars(c, 3));
-        rr = std::sqrt(c->host_scal[2]) / bnorm;
+        // initial residual in FP64, cast to FP32.  From p = 0 it is b0 itself
+        // (L 0 = 0 exactly) and rr = 1: a cast, and the first update reads no p.
+        bool p_zero = false;
+        if (zero_guess && res_tiled_ok(F0.d, sizeof(double))) {
+            TRY(convert<double, float>(c, c->b0, n, r32));
+            rr = 1.0;
+            p_zero = true;
+        } else {
+            if (zero_guess) TRY(fill<double>(c, cur, n, 0.0));
+            TRY(outer_update(c, cur, nullptr, other, r32, 2));
+            std::swap(cur, other);
+            TRY(fetch_scalars(c, 3));
+            rr = std::sqrt(c->host_scal[2]) / bnorm;
+        }
         if (st) st->hist[0] = rr;
         best = rr;
         if (!std::isfinite(rr)) status = MG_ENONFINITE;
@@ -687,7 +700,8 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
             float* ex = F0.f32.x;
             float* et = F0.f32.t;
             TRY(vcycle<float>(c, 0, &ex, &et, r32, true));
-            TRY(outer_update(c, cur, ex, other, r32, 2));
+            TRY(outer_update(c, p_zero ? nullptr : cur, ex, other, r32, 2));
+            p_zero = false;
             std::swap(cur, other);
             ++cycles;
             TRY(fetch_scalars(c, 3));
@@ -698,6 +712,7 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
             best = std::min(best, rr);
             if (rr > 1e3 * best) break;
         }
+        if (p_zero) TRY(fill<double>(c, cur, n, 0.0));  // stopped before any update: p = 0
     }
 
     // zero-mean result in the caller's buffer

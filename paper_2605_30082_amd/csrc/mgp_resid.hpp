@@ -1,8 +1,8 @@
 // Residual-type stencil passes r = b - L x on one level, marching in z:
 //   RES_NORM      partial sums of ||r||^2 (FP64 convergence test)
 //   RES_RESTRICT  coarse rhs = mean of the 8 children of r (multigrid restriction)
-//   RES_OUTER     mixed-precision outer step: q = p + e (e FP32), r = b - L q,
-//                 p_out = q, r32 = (float) r, partial sums of ||r||^2
+//   RES_OUTER     mixed-precision outer step: q = p + e (e FP32; p NULL reads as
+//                 zeros), r = b - L q, p_out = q, r32 = (float) r, partial sums of ||r||^2
 // A block owns a 64 x 32 tile of (x, y) and a chunk of z (tall tiles: the 1-cell
 // ring of x re-read by neighbouring tiles is 1/16 of a tile row count, not 1/4).  Each thread owns a
 // pair of x-adjacent cells of one row.  Per z-step s it writes plane s+1 of x
@@ -120,7 +120,7 @@ k_resid(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict_
     const auto r_bx = make_rsrc(bx, (unsigned)(n_fx(d) * sizeof(T)));
     const auto r_by = make_rsrc(by, (unsigned)(n_fy(d) * sizeof(T)));
     const auto r_bz = make_rsrc(bz, (unsigned)(n_fz(d) * sizeof(T)));
-    const auto r_x = make_rsrc(x, (unsigned)(ncell * sizeof(T)));
+    const auto r_x = make_rsrc(x, x ? (unsigned)(ncell * sizeof(T)) : 0u);  // x NULL: an iterate of zeros
     const auto r_e = make_rsrc(e ? (const void*)e : (const void*)x, e ? (unsigned)(ncell * sizeof(float)) : 0u);
     const auto r_rho = make_rsrc(RHO ? (const void*)rho : (const void*)x, RHO ? (unsigned)(ncell * sizeof(T)) : 0u);
     const auto r_null = make_rsrc(x, 0u);

@@ -135,7 +135,8 @@ def test_kernel_timing_stats(density):
         n = st.cycles
         if precision == "mixed":
             # at 64^3 only the finest grid is wide enough for the tiled kernels
-            expect = {L.MG_K_SWEEP2: 2 * n, L.MG_K_RESTRICT: n, L.MG_K_PROLONG: n, L.MG_K_OUTER: n + 1}
+            # (from p = 0 the initial residual is the rhs itself: no outer update before cycle 1)
+            expect = {L.MG_K_SWEEP2: 2 * n, L.MG_K_RESTRICT: n, L.MG_K_PROLONG: n, L.MG_K_OUTER: n}
         else:
             # the first cycle runs both pre-sweeps; every later one starts with the
             # sweep that also takes the norm of the previous result, and so does the
@@ -188,3 +189,23 @@ def test_density_context_on_unusual_grids(dims):
         with S.Solver(*faces, h, **kw) as s:
             pf, stf = s.solve(T(rhs), 1e-10)
         assert torch.equal(pd, pf) and std.cycles == stf.cycles
+
+
+@pytest.mark.parametrize("density", [False, True])
+def test_mixed_zero_guess_without_cycles(density):
+    """From p = 0 the mixed loop starts from the rhs itself; a tolerance the start
+    already meets returns p = 0 whatever the caller's buffer held."""
+    wl = W.drop_film_workload(64)
+    gb, gd = gpu_inputs(wl)
+    rho = S.density_from_vof(T(wl.f_drop), T(wl.f_film), wl.rho_drop, wl.rho_film, wl.rho_gas)
+    kw = dict(precision="mixed", zero_guess=True)
+    s = S.Solver.from_density(rho, wl.h, **kw) if density else S.Solver(*gb, wl.h, **kw)
+    garbage = torch.randn(gd.shape, dtype=torch.float64, device=gd.device)
+    p, st = s.solve(gd, 2.0, p=garbage)
+    assert st.cycles == 0 and st.hist[0] == 1.0
+    assert torch.count_nonzero(p) == 0
+    # and a full solve from the same garbage buffer equals one from a zero buffer
+    p1, st1 = s.solve(gd, 1e-10, p=torch.randn(gd.shape, dtype=torch.float64, device=gd.device))
+    p2, st2 = s.solve(gd, 1e-10, p=torch.zeros_like(gd))
+    assert torch.equal(p1, p2) and st1.hist == st2.hist
+    s.close()

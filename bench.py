@@ -5,7 +5,9 @@ Workload: 512^3 cells on the unit cube, a silicone-oil film (z < 0.1, 960 kg/m^3
 under 32 seeded non-overlapping water drops (radii 0.02..0.06, 1000 kg/m^3) in
 air (1.2 kg/m^3); VOF fractions by 4^3 sub-cell sampling; rhs = divergence of a
 seeded uniform [-1, 1] face velocity; homogeneous Neumann walls; tolerance 1e-10
-on the relative residual.
+on the relative residual.  --workload drop_film / spheroid_film / sphere run the
+smaller layouts (a drop above the film at 128^3, an oblate spheroid touching it at
+256^3, a lone sphere at 32^3) through the same steps; --n changes the size.
 
 One step = the whole hot path on that input, all on the GPU:
   update   new coefficients (the cell density; --coefficients faces: the three
@@ -98,8 +100,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=512, help="cells per axis (default 512)")
-    ap.add_argument("--drops", type=int, default=32)
+    ap.add_argument("--workload", choices=["many_drops", "drop_film", "spheroid_film", "sphere"],
+                    default="many_drops", help="density layout (default: film + 32 drops)")
+    ap.add_argument("--n", type=int, default=None,
+                    help="cells per axis (default: the layout's own size, 512 / 128 / 256 / 32)")
+    ap.add_argument("--drops", type=int, default=32, help="drop count of the many_drops layout")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solves")
@@ -173,18 +178,25 @@ def measure_copy_gbps(stream) -> float:
     return 2.0 * (1 << 30) / (statistics.median(times) * 1e-3) / 1e9
 
 
-GOLDEN = os.path.join(ROOT, "tests", "golden", "many_drops512_oracle.txt")
+def golden_path(workload, n, drops):
+    """Stored sampled oracle solutions of this workload (tests/golden/<layout><N>_oracle.txt,
+    written by tests/golden/make_oracle_samples.py), or None."""
+    if workload == "many_drops" and drops != 32:
+        return None
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}{n}_oracle.txt")
+    return path if os.path.exists(path) else None
 
 
-def sampled_error_vs_oracle(p, n, drops, tol):
+def sampled_error_vs_oracle(p, workload, n, drops):
     """Relative RMS error of p on the cells sampled in the stored oracle solution of
-    the 512^3 film + 32 drops workload converged to 1e-12 (None for other workloads)."""
+    the workload converged to 1e-12 (None where no samples are stored)."""
     import numpy as np
     import torch
-    if n != 512 or drops != 32 or not os.path.exists(GOLDEN):
+    path = golden_path(workload, n, drops)
+    if path is None:
         return None
     meta, idx, val = {}, [], []
-    with open(GOLDEN) as f:
+    with open(path) as f:
         for line in f:
             if line.startswith("#"):
                 parts = line[1:].split()
@@ -202,7 +214,14 @@ def sampled_error_vs_oracle(p, n, drops, tol):
     d = got - np.array(val)
     return {"sampled_rel_rms": float(np.sqrt(np.mean(d ** 2)) / rms),
             "sampled_max": float(np.abs(d).max() / rms), "cells": len(idx),
-            "reference": "oracle FP64 V-cycles to rr 1e-12, tests/golden/many_drops512_oracle.txt"}
+            "reference": f"oracle FP64 V-cycles to rr 1e-12, {os.path.relpath(path, ROOT)}"}
+
+
+def layout_text(args) -> str:
+    return {"many_drops": f"film z<0.1 (rho 960) + {args.drops} drops (1000) in air (1.2)",
+            "drop_film": "film z<0.15 (rho 960) + drop r=0.12 (1000) in air (1.2)",
+            "spheroid_film": "film z<0.15 (rho 960) + oblate spheroid touching it (1000) in air (1.2)",
+            "sphere": "sphere r=0.25 (rho 1000) in air (1.2)"}[args.workload]
 
 
 def copy_calibration() -> int:
@@ -239,11 +258,11 @@ def main() -> int:
     S.L.load()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    n = args.n
-    cells = n ** 3
-
     t0 = time.time()
-    wl = W.many_drops_workload(n, count=args.drops)
+    kw = {"count": args.drops} if args.workload == "many_drops" else {}
+    wl = W.make(args.workload, args.n, **kw)
+    n = wl.dims[0]
+    cells = n ** 3
     w_np = W.loss_weights(wl.dims)
     log(f"workload {wl.name} {n}^3 generated in {time.time() - t0:.1f} s")
 
@@ -274,11 +293,19 @@ def main() -> int:
 
     stream = torch.cuda.current_stream()
     mixed = make(precision="mixed", zero_guess=True, timing=True)
-    # inside the timed steps only the dominant kernel (the two-sweep smoother) carries
-    # timing events: each timed launch costs the GPU a few microseconds before it
-    mixed.set_timing_classes([S.L.MG_K_SWEEP2])
     p = torch.zeros_like(rhs)
     lam = torch.zeros_like(rhs)
+    # inside the timed steps only the dominant kernel class carries timing events (each
+    # timed launch costs the GPU a few microseconds before it): one untimed forward +
+    # adjoint solve with every class timed picks it (the two-sweep smoother wherever a
+    # level is wide enough for it)
+    _, st_probe = mixed.solve(rhs, args.tol, p=p)
+    _, sta_probe = mixed.solve_adjoint(w, args.tol, lam=lam)
+    torch.cuda.synchronize()
+    probe_ms = [a + b for a, b in zip(st_probe.kernel_ms, sta_probe.kernel_ms)]
+    timed_class = max(range(len(KERNEL_NAMES)), key=lambda k: probe_ms[k])
+    mixed.set_timing_classes([timed_class])
+    log(f"timed kernel class inside the steps: {KERNEL_NAMES[timed_class]}")
 
     def step(record):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
@@ -325,10 +352,10 @@ def main() -> int:
     torch.cuda.synchronize()
     ksum_all = kernel_summary([st_all, sta_all], "mixed", coef)
     dominant = max(ksum_all, key=lambda k: ksum_all[k]["ms_total"]) if ksum_all else None
-    if dominant not in ksum:
+    if dominant is not None and dominant not in ksum:
         raise RuntimeError(f"dominant kernel class {dominant} was not timed inside the timed steps")
     setup_ms = solve_stats[-1].setup_ms
-    err_vs_oracle = sampled_error_vs_oracle(p, n, args.drops, args.tol)
+    err_vs_oracle = sampled_error_vs_oracle(p, args.workload, n, args.drops)
     copy_gbps = measure_copy_gbps(stream)
     log(f"copy {copy_gbps:.0f} GB/s; mixed solve {mixed_ms:.2f} ms")
 
@@ -429,7 +456,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"film + {args.drops} drops, {n}^3 cells, rho 960/1000/1.2, Neumann, tol {args.tol:g}",
+        "config": {"workload": f"{layout_text(args)}, {n}^3 cells, Neumann, tol {args.tol:g}",
                    "n": n, "cells": cells, "levels": mixed.num_levels, "precision": "mixed (FP32 V-cycle, FP64 outer)",
                    "pre_post_sweeps": [2, 2], "tol": args.tol, "coefficients": coef},
         "mixed": {"time_to_tol_ms": mixed_ms, "cycles": mixed_cycles, "rel_res_max": mixed_rr,

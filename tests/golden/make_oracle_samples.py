@@ -1,11 +1,13 @@
-"""Writes tests/golden/many_drops512_oracle.txt: sampled values of the oracle's
-solutions of the 512^3 film + 32 drops workload, FP64 V-cycles (2+2 red-black
-sweeps) from a zero guess, stopped at two relative residuals:
+"""Writes tests/golden/<layout><N>_oracle.txt: sampled values of the oracle's
+solutions of one seeded workload, FP64 V-cycles (2+2 red-black sweeps) from a
+zero guess, stopped at two relative residuals:
   tol10  ||r|| <= 1e-10 ||b||  (the stopping rule of the benchmark solve)
   tol12  ||r|| <= 1e-12 ||b||  (converged: reference for a tighter GPU solve)
 Calls only the oracle and the seeded input generator.
 
-Run: python tests/golden/make_many_drops512.py   (about 10 GB of host memory, minutes)
+Run: python tests/golden/make_oracle_samples.py many_drops 512     (about 10 GB of host memory, minutes)
+     python tests/golden/make_oracle_samples.py drop_film 128
+     python tests/golden/make_oracle_samples.py spheroid_film 256
 """
 import os
 import sys
@@ -20,15 +22,23 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 from paper_2605_30082_amd import workloads as W  # noqa: E402
 
-N = 512
 NSAMPLES = 4096
 SAMPLE_SEED = 4
 TOLS = (("tol10", 1e-10), ("tol12", 1e-12))
 
 
+LAYOUT_TEXT = {
+    "many_drops": "film + 32 drops workload (seeded inputs: velocity 0,\n# drops 1)",
+    "drop_film": "film + one drop workload (seeded input: velocity 0)",
+    "spheroid_film": "film + oblate spheroid workload (seeded input: velocity 0)",
+    "sphere": "sphere workload (seeded input: velocity 0)",
+}
+
+
 def main():
+    layout, N = sys.argv[1], int(sys.argv[2])
     t0 = time.time()
-    wl = W.many_drops_workload(N)
+    wl = W.make(layout, N)
     beta = oracle.faces_from_vof(wl.f_drop, wl.f_film, wl.rho_drop, wl.rho_film, wl.rho_gas)
     b = oracle.divergence(wl.u, wl.v, wl.w, wl.h, wl.dt)
     del wl
@@ -43,12 +53,12 @@ def main():
         meta.append((name, res.cycles, res.rel_res, float(np.linalg.norm(p)), float(p.mean()),
                      res.rhs_mean))
         del res, p
-    out = os.path.join(HERE, "many_drops512_oracle.txt")
+    out = os.path.join(HERE, f"{layout}{N}_oracle.txt")
     with open(out, "w") as f:
-        f.write("# Oracle solutions of the 512^3 film + 32 drops workload (seeded inputs: velocity 0,\n")
-        f.write("# drops 1), FP64 V-cycles (2+2 red-black sweeps) from a zero guess, stopped at\n")
-        f.write("# ||r|| <= 1e-10 ||b|| (tol10) and ||r|| <= 1e-12 ||b|| (tol12).\n")
-        f.write("# Written by tests/golden/make_many_drops512.py, which calls only oracle/.\n")
+        f.write(f"# Oracle solutions of the {N}^3 {LAYOUT_TEXT[layout]}, FP64 V-cycles (2+2 red-black\n")
+        f.write("# sweeps) from a zero guess, stopped at ||r|| <= 1e-10 ||b|| (tol10) and\n")
+        f.write("# ||r|| <= 1e-12 ||b|| (tol12).\n")
+        f.write(f"# Written by tests/golden/make_oracle_samples.py {layout} {N}, which calls only oracle/.\n")
         for name, cyc, rr, n2, mean, rm in meta:
             f.write(f"# {name}_cycles {cyc}\n# {name}_rel_res {rr:.17g}\n")
             f.write(f"# {name}_norm2 {n2:.17g}\n# {name}_mean {mean:.17g}\n")

@@ -1,11 +1,12 @@
 """Parity at the benchmark's full size and launch configuration (512^3, the film +
-32 drops workload), and at the 256^3 mixed-precision configuration.
+32 drops workload), at the 128^3 drop-film FP64 configuration and at the 256^3
+mixed-precision configuration.
 
 At 512^3 the oracle runs single kernels over the whole grid (a pass takes about
 a second on the host cores), recomputes the residual of the GPU solutions, and
 supplies sampled values of its own solutions stopped at relative residuals of
-1e-10 and 1e-12 (tests/golden/many_drops512_oracle.txt, written by
-make_many_drops512.py).
+1e-10 and 1e-12 (tests/golden/<layout><N>_oracle.txt, written by
+make_oracle_samples.py).
 The exact z-layered solution (tridiagonal reduction, the real 960/1.2 density
 jump) is checked at 512^3 as a property that holds at any size.
 """
@@ -24,7 +25,7 @@ pytestmark = pytest.mark.gpu
 
 S = pytest.importorskip("paper_2605_30082_amd.solver")
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "many_drops512_oracle.txt")
+GOLDEN_DIR = os.path.join(os.path.dirname(__file__), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -42,9 +43,9 @@ def true_rr(ob, od, p, h):
     return float(np.linalg.norm(oracle.residual(ob, b, p, h)) / np.linalg.norm(b))
 
 
-def read_golden():
+def read_golden(name="many_drops512"):
     meta, rows = {}, []
-    with open(GOLDEN) as f:
+    with open(os.path.join(GOLDEN_DIR, f"{name}_oracle.txt")) as f:
         for line in f:
             if line.startswith("#"):
                 parts = line[1:].split()
@@ -180,6 +181,9 @@ def test_spheroid_film_256_mixed():
     gb, gd = gpu_inputs(wl)
     ob, od = oracle_inputs(wl)
     exact = oracle.solve(ob, od, wl.h, tol=1e-12).p
+    meta, idx, val = read_golden("spheroid_film256")
+    # the stored samples are the solution computed here
+    assert max_rel(exact.ravel()[idx], val["tol12"]) < 1e-12
     out = {}
     for precision in ("fp64", "mixed"):
         s = S.Solver(*gb, wl.h, precision=precision, zero_guess=True)
@@ -189,7 +193,31 @@ def test_spheroid_film_256_mixed():
         note(f"spheroid 256^3 {precision}: cycles {st.cycles} rel err {err:.3e}")
         assert err < 1e-9
         assert true_rr(ob, od, out[precision], wl.h) <= 1.000001e-10
+        assert st.cycles == meta["tol10_cycles"]
         s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_drop_film_128_against_stored_oracle(precision):
+    """The plain-FP64 configuration at 128^3 (and the mixed solve of it): the same
+    number of V-cycles as the oracle under the same stopping rule, and its sampled
+    solution to rounding order (FP64) or to the FP32 preconditioner's level (mixed)."""
+    wl = W.drop_film_workload(128)
+    gb, gd = gpu_inputs(wl)
+    meta, idx, val = read_golden("drop_film128")
+    with S.Solver(*gb, wl.h, precision=precision, zero_guess=True) as s:
+        p, st = s.solve(gd, 1e-10)
+    pg = N(p)
+    rms = meta["tol10_norm2"] / np.sqrt(128 ** 3)
+    d = pg.ravel()[idx] - val["tol10"]
+    sampled = float(np.sqrt(np.mean(d ** 2)) / rms)
+    note(f"drop film 128^3 {precision}: cycles {st.cycles} (oracle {meta['tol10_cycles']:.0f}), "
+         f"sampled rel vs oracle {sampled:.3e}")
+    assert st.cycles == meta["tol10_cycles"] and st.rel_res <= 1e-10
+    bound = 1e-11 if precision == "fp64" else 1e-9
+    assert sampled < bound and float(np.abs(d).max()) / rms < 10 * bound
+    d12 = pg.ravel()[idx] - val["tol12"]
+    assert float(np.sqrt(np.mean(d12 ** 2))) / rms < 1e-9
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])

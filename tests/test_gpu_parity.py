@@ -245,6 +245,7 @@ def test_solve_fp64_lockstep_sphere32():
 
 
 @pytest.mark.parametrize("make,n,precision", [
+    (W.sphere_workload, 32, "fp64"),
     (W.sphere_workload, 32, "mixed"),
     (W.drop_film_workload, 128, "fp64"),
     (W.drop_film_workload, 128, "mixed"),

@@ -74,12 +74,18 @@ enum {
                                 (lambda) and start from zero */
     MG_FLAG_TIMING = 2,      /* time every launch of the finest-grid kernels with HIP events
                                 and report the totals in mg_stats */
-    MG_FLAG_FCG = 4          /* solve by flexible conjugate gradients with one V-cycle (of
+    MG_FLAG_FCG = 4,         /* solve by flexible conjugate gradients with one V-cycle (of
                                 the context's precision) as the preconditioner, one previous
                                 direction kept; mg_stats.cycles then counts iterations.
                                 Costs three more FP64 cell arrays.  The plain V-cycle
                                 iteration (flag clear) is the method of the paper's solver;
                                 this is a Krylov acceleration of it. */
+    MG_FLAG_LEVEL_LAUNCHES = 8  /* run every level of a V-cycle with one launch per kernel.  By
+                                default the levels of at most 4096 cells that no tiled kernel
+                                serves (16^3 and below; every level of grids that small) run
+                                in one single-workgroup launch with the same per-cell
+                                arithmetic: identical results, a dozen launches fewer per
+                                level.  For comparison and testing. */
 };
 
 /*

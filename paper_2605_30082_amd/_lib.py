@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(PKG, "libmgp.so")
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EHIP, MG_ENOCONV, MG_ENONFINITE = 0, -1, -2, -3, -4, -5
 MG_BC_NEUMANN = 0
 MG_PREC_FP64, MG_PREC_MIXED = 0, 1
-MG_FLAG_ZERO_GUESS, MG_FLAG_TIMING, MG_FLAG_FCG = 1, 2, 4
+MG_FLAG_ZERO_GUESS, MG_FLAG_TIMING, MG_FLAG_FCG, MG_FLAG_LEVEL_LAUNCHES = 1, 2, 4, 8
 MG_HIST_MAX = 256
 MG_MAX_LEVELS = 16
 MG_K_SWEEP, MG_K_RESTRICT, MG_K_PROLONG, MG_K_OUTER, MG_K_NORM, MG_K_SWEEP2, MG_K_COUNT = 0, 1, 2, 3, 4, 5, 6

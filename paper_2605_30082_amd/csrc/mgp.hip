@@ -17,6 +17,7 @@
 #include "mgp_sweep2.hpp"
 #include "mgp_krylov.hpp"
 #include "mgp_resid.hpp"
+#include "mgp_tail.hpp"
 #include "mgp_transfer.hpp"
 
 using namespace mgp;
@@ -63,6 +64,12 @@ struct mg_ctx {
     bool use_rho = false;        // finest FP64 passes form coefficients from rho
     double* scal = nullptr;      // device scalars
     double* host_scal = nullptr; // pinned host mirror
+    // levels tail_lev..nlev-1 run as one single-workgroup launch (-1: none)
+    int tail_lev = -1;
+    TailLevel<double>* tail64 = nullptr;  // device tables (arena)
+    TailLevel<float>* tail32 = nullptr;
+    TailLevel<double> tail64_h[MG_MAX_LEVELS];  // their host images
+    TailLevel<float> tail32_h[MG_MAX_LEVELS];
     void* arena = nullptr;
     size_t arena_bytes = 0;
     double setup_ms = 0.0;
@@ -328,6 +335,25 @@ int coarse_apply(mg_ctx* c, const T* r, T* e)
 }
 
 template <typename T>
+TailLevel<T>* tail_tab(mg_ctx* c);
+template <>
+TailLevel<double>* tail_tab<double>(mg_ctx* c) { return c->tail64; }
+template <>
+TailLevel<float>* tail_tab<float>(mg_ctx* c) { return c->tail32; }
+
+// The V-cycle from level l (>= tail_lev) down, in one launch; same contract as vcycle().
+template <typename T>
+int vcycle_tail(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init, int pre_done)
+{
+    const int pre = c->opts.pre, post = c->opts.post;
+    k_vcycle_tail<T><<<1, kTailNT, 0, c->stream>>>(tail_tab<T>(c), l, c->nlev, c->G, *x, *t, b, pre, post,
+                                                   zero_init ? 1 : 0, pre_done);
+    CHECK_LAUNCH(c);
+    if (((pre - pre_done) + post) & 1) std::swap(*x, *t);
+    return MG_OK;
+}
+
+template <typename T>
 int fill(mg_ctx* c, T* x, long n, T v)
 {
     k_fill<T><<<grid_for(n), kBlock, 0, c->stream>>>(x, n, v);
@@ -357,6 +383,7 @@ int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init, int pre_d
 {
     Level& L = c->lev[l];
     if (l == c->nlev - 1) return coarse_apply<T>(c, b, *x);
+    if (c->tail_lev >= 0 && l >= c->tail_lev) return vcycle_tail<T>(c, l, x, t, b, zero_init, pre_done);
     const int pre = c->opts.pre, post = c->opts.post;
     if (zero_init && pre == 0) TRY(fill<T>(c, *x, L.n, (T)0));
     TRY(smooth<T>(c, l, b, x, t, 0, pre - pre_done, zero_init && pre_done == 0));
@@ -783,6 +810,8 @@ void carve(mg_ctx* c, Arena& a)
     c->work = a.take<double>(std::max<long>(m * 2 * m, n0));
     c->partials = a.take<double>(kMaxPartials);
     c->scal = a.take<double>(16);
+    c->tail64 = a.take<TailLevel<double>>(MG_MAX_LEVELS);
+    if (c->mixed) c->tail32 = a.take<TailLevel<float>>(MG_MAX_LEVELS);
     if (c->use_rho) c->rho = a.take<double>(n0);
     if (c->opts.flags & MG_FLAG_FCG) {
         c->fr = a.take<double>(n0);
@@ -808,6 +837,48 @@ void carve(mg_ctx* c, Arena& a)
             L.f32.b = a.take<float>(L.n);
         }
     }
+}
+
+// First level of the single-workgroup tail: the deepest run of levels, ending
+// at the coarsest, that have at most kTailCells cells and that no tiled kernel
+// serves in either precision (so the tail repeats exactly the per-level
+// kernels), and that fit its LDS together.  -1 if that run is the coarsest
+// level alone or MG_FLAG_LEVEL_LAUNCHES asks for one launch per kernel.
+int tail_start(const mg_ctx* c)
+{
+    if (c->opts.flags & MG_FLAG_LEVEL_LAUNCHES) return -1;
+    int l0 = c->nlev;
+    for (int l = c->nlev - 1; l >= 0; --l) {
+        const Dims& d = c->lev[l].d;
+        const bool simple = c->lev[l].n <= kTailCells && !sweep_is_fused(d, 4) && !sweep_is_fused(d, 8) &&
+                            !sweep2_ok(d, 4) && !res_tiled_ok(d, 4) && !res_tiled_ok(d, 8) && !pro_tiled_ok(d, 4) &&
+                            !pro_tiled_ok(d, 8);
+        if (!simple) break;
+        l0 = l;
+    }
+    long cells = 0;
+    for (int l = l0; l < c->nlev; ++l) cells += c->lev[l].n;
+    if (cells > kTailLds || c->nlev - l0 > kTailMaxLevels) return -1;
+    return l0 < c->nlev - 1 ? l0 : -1;
+}
+
+// The tail's level tables (their buffers never move after carve()).
+int upload_tail(mg_ctx* c)
+{
+    c->tail_lev = tail_start(c);
+    if (c->tail_lev < 0) return MG_OK;
+    for (int l = 0; l < c->nlev; ++l) {
+        const Level& L = c->lev[l];
+        const double h2 = L.h * L.h;
+        c->tail64_h[l] = {L.f64.bx, L.f64.by, L.f64.bz, L.f64.b, L.f64.x, L.f64.t, L.d, h2, 1.0 / h2};
+        if (c->mixed)
+            c->tail32_h[l] = {L.f32.bx, L.f32.by, L.f32.bz, L.f32.b, L.f32.x, L.f32.t, L.d, (float)h2,
+                              (float)(1.0 / h2)};
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->tail64, c->tail64_h, sizeof(c->tail64_h), hipMemcpyHostToDevice, c->stream));
+    if (c->mixed)
+        HIP_TRY(c, hipMemcpyAsync(c->tail32, c->tail32_h, sizeof(c->tail32_h), hipMemcpyHostToDevice, c->stream));
+    return MG_OK;
 }
 
 // Finest-level coefficients from the caller's faces, or (rho != NULL) from a
@@ -933,7 +1004,7 @@ int setup_ctx(mg_ctx** out, const double* beta_x, const double* beta_y, const do
     if (o.pre < 0 || o.pre > 8 || o.post < 0 || o.post > 8 || o.pre + o.post == 0 || o.max_cycles < 1 ||
         o.max_cycles >= MG_HIST_MAX || o.coarse_max < 1 || o.coarse_max > 4 ||
         (o.precision != MG_PREC_FP64 && o.precision != MG_PREC_MIXED) ||
-        (o.flags & ~(MG_FLAG_ZERO_GUESS | MG_FLAG_TIMING | MG_FLAG_FCG))) {
+        (o.flags & ~(MG_FLAG_ZERO_GUESS | MG_FLAG_TIMING | MG_FLAG_FCG | MG_FLAG_LEVEL_LAUNCHES))) {
         set_err(c, "invalid options");
         return fail(MG_EINVAL);
     }
@@ -989,6 +1060,8 @@ int setup_ctx(mg_ctx** out, const double* beta_x, const double* beta_y, const do
                 return fail(MG_EHIP);
             }
     }
+    const int su = upload_tail(c);
+    if (su != MG_OK) return fail(su);
     const int st = setup_impl(c, beta_x, beta_y, beta_z, rho);
     if (st != MG_OK) return fail(st);
     c->valid = true;

@@ -334,11 +334,12 @@ __global__ void k_coarse_inverse(const double* __restrict__ bx, const double* __
     if (threadIdx.x == 0) status[0] = singular ? 1.0 : 0.0;
 }
 
-// e = G r on the coarsest level (n <= 64 cells), accumulated in FP64
+// e = G r on the coarsest level (n <= 64 cells), accumulated in FP64, by the
+// first n threads of a block; rs: 64 doubles of LDS
 template <typename T>
-__global__ void k_coarse_apply(const double* __restrict__ G, int n, const T* __restrict__ r, T* __restrict__ e)
+__device__ inline void coarse_apply_block(const double* __restrict__ G, int n, const T* __restrict__ r,
+                                          T* __restrict__ e, double* rs)
 {
-    __shared__ double rs[64];
     const int t = threadIdx.x;
     if (t < n) rs[t] = (double)r[t];
     __syncthreads();
@@ -347,6 +348,13 @@ __global__ void k_coarse_apply(const double* __restrict__ G, int n, const T* __r
         for (int j = 0; j < n; ++j) s += G[(long)t * n + j] * rs[j];
         e[t] = (T)s;
     }
+}
+
+template <typename T>
+__global__ void k_coarse_apply(const double* __restrict__ G, int n, const T* __restrict__ r, T* __restrict__ e)
+{
+    __shared__ double rs[64];
+    coarse_apply_block<T>(G, n, r, e, rs);
 }
 
 // ---------------------------------------------------------------------------
@@ -416,16 +424,10 @@ __global__ void k_residual_norm(const double* __restrict__ bx, const double* __r
 // colour is taken as 0.  A cell with no coupled face copies its old value.
 // Launch: grid (ceil(ceil(nx/2)/64), ceil(ny/4), nz), block (64, 4).
 template <typename T>
-__global__ void k_half_sweep(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
-                             Dims d, T h2, const T* __restrict__ b, const T* src, T* dst, int colour,
-                             int zero_src)
+__device__ inline T half_sweep_value(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
+                                     const Dims d, T h2, const T* __restrict__ b, const T* src, int zero_src, int i,
+                                     int j, int k)
 {
-    const int m = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    const int k = blockIdx.z;
-    if (j >= d.ny) return;
-    const int i = 2 * m + ((j + k + colour) & 1);
-    if (i >= d.nx) return;
     const long c = ((long)k * d.ny + j) * d.nx + i;
     T dg, of;
     if (zero_src) {
@@ -443,10 +445,50 @@ __global__ void k_half_sweep(const T* __restrict__ bx, const T* __restrict__ by,
     T v;
     if (dg > (T)0) v = (of - h2 * b[c]) / dg;
     else v = zero_src ? (T)0 : src[c];
-    dst[c] = v;
+    return v;
+}
+
+template <typename T>
+__device__ inline void half_sweep_cell(const T* __restrict__ bx, const T* __restrict__ by,
+                                       const T* __restrict__ bz, const Dims d, T h2, const T* __restrict__ b,
+                                       const T* src, T* dst, int zero_src, int i, int j, int k)
+{
+    dst[((long)k * d.ny + j) * d.nx + i] = half_sweep_value<T>(bx, by, bz, d, h2, b, src, zero_src, i, j, k);
+}
+
+template <typename T>
+__global__ void k_half_sweep(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
+                             Dims d, T h2, const T* __restrict__ b, const T* src, T* dst, int colour,
+                             int zero_src)
+{
+    const int m = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.y * 4 + threadIdx.y;
+    const int k = blockIdx.z;
+    if (j >= d.ny) return;
+    const int i = 2 * m + ((j + k + colour) & 1);
+    if (i >= d.nx) return;
+    half_sweep_cell<T>(bx, by, bz, d, h2, b, src, dst, zero_src, i, j, k);
 }
 
 // b_coarse = mean over the 8 children of (b - L x) (fine dims f, coarse dims c)
+template <typename T>
+__device__ inline T restrict_cell(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
+                                  const Dims f, T inv_h2, const T* __restrict__ b, const T* __restrict__ x, int I,
+                                  int J, int K)
+{
+    T s = 0;
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+                const int i = 2 * I + cx, j = 2 * J + cy, k = 2 * K + cz;
+                const long c = ((long)k * f.ny + j) * f.nx + i;
+                T dg, of;
+                stencil(bx, by, bz, x, f, i, j, k, c, dg, of);
+                s += b[c] - (of - dg * x[c]) * inv_h2;
+            }
+    return s * (T)0.125;
+}
+
 template <typename T>
 __global__ void k_residual_restrict(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
                                     Dims f, Dims cd, T inv_h2, const T* __restrict__ b, const T* __restrict__ x,
@@ -456,47 +498,48 @@ __global__ void k_residual_restrict(const T* __restrict__ bx, const T* __restric
     for (long C = (long)blockIdx.x * kBlock + threadIdx.x; C < n; C += (long)gridDim.x * kBlock) {
         int I, J, K;
         cell_of(C, cd, I, J, K);
-        T s = 0;
-        for (int cz = 0; cz < 2; ++cz)
-            for (int cy = 0; cy < 2; ++cy)
-                for (int cx = 0; cx < 2; ++cx) {
-                    const int i = 2 * I + cx, j = 2 * J + cy, k = 2 * K + cz;
-                    const long c = ((long)k * f.ny + j) * f.nx + i;
-                    T dg, of;
-                    stencil(bx, by, bz, x, f, i, j, k, c, dg, of);
-                    s += b[c] - (of - dg * x[c]) * inv_h2;
-                }
-        bc[C] = s * (T)0.125;
+        bc[C] = restrict_cell<T>(bx, by, bz, f, inv_h2, b, x, I, J, K);
     }
 }
 
 // x_fine += trilinear prolongation of the coarse correction e
 template <typename T>
+__device__ inline T prolong_value(const Dims f, const Dims cd, const T* __restrict__ e, long c)
+{
+    int i, j, k;
+    cell_of(c, f, i, j, k);
+    const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+    int I1 = (i & 1) ? I0 + 1 : I0 - 1;
+    int J1 = (j & 1) ? J0 + 1 : J0 - 1;
+    int K1 = (k & 1) ? K0 + 1 : K0 - 1;
+    I1 = I1 < 0 ? 0 : (I1 > cd.nx - 1 ? cd.nx - 1 : I1);
+    J1 = J1 < 0 ? 0 : (J1 > cd.ny - 1 ? cd.ny - 1 : J1);
+    K1 = K1 < 0 ? 0 : (K1 > cd.nz - 1 ? cd.nz - 1 : K1);
+    const long sy = cd.nx, sz = (long)cd.nx * cd.ny;
+    auto E = [&](int a, int bb, int cc) { return e[(long)cc * sz + (long)bb * sy + a]; };
+    // x-direction first, then y, then z: weights 3/4 (parent) and 1/4 (side)
+    const T q = (T)0.75, o = (T)0.25;
+    const T e00 = q * E(I0, J0, K0) + o * E(I1, J0, K0);
+    const T e10 = q * E(I0, J1, K0) + o * E(I1, J1, K0);
+    const T e01 = q * E(I0, J0, K1) + o * E(I1, J0, K1);
+    const T e11 = q * E(I0, J1, K1) + o * E(I1, J1, K1);
+    const T f0 = q * e00 + o * e10;
+    const T f1 = q * e01 + o * e11;
+    return q * f0 + o * f1;
+}
+
+template <typename T>
+__device__ inline void prolong_cell(const Dims f, const Dims cd, const T* __restrict__ e, T* __restrict__ x, long c)
+{
+    x[c] += prolong_value<T>(f, cd, e, c);
+}
+
+template <typename T>
 __global__ void k_prolong_correct(Dims f, Dims cd, const T* __restrict__ e, T* __restrict__ x)
 {
     const long n = (long)f.nx * f.ny * f.nz;
-    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
-        int i, j, k;
-        cell_of(c, f, i, j, k);
-        const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
-        int I1 = (i & 1) ? I0 + 1 : I0 - 1;
-        int J1 = (j & 1) ? J0 + 1 : J0 - 1;
-        int K1 = (k & 1) ? K0 + 1 : K0 - 1;
-        I1 = I1 < 0 ? 0 : (I1 > cd.nx - 1 ? cd.nx - 1 : I1);
-        J1 = J1 < 0 ? 0 : (J1 > cd.ny - 1 ? cd.ny - 1 : J1);
-        K1 = K1 < 0 ? 0 : (K1 > cd.nz - 1 ? cd.nz - 1 : K1);
-        const long sy = cd.nx, sz = (long)cd.nx * cd.ny;
-        auto E = [&](int a, int bb, int cc) { return e[(long)cc * sz + (long)bb * sy + a]; };
-        // x-direction first, then y, then z: weights 3/4 (parent) and 1/4 (side)
-        const T q = (T)0.75, o = (T)0.25;
-        const T e00 = q * E(I0, J0, K0) + o * E(I1, J0, K0);
-        const T e10 = q * E(I0, J1, K0) + o * E(I1, J1, K0);
-        const T e01 = q * E(I0, J0, K1) + o * E(I1, J0, K1);
-        const T e11 = q * E(I0, J1, K1) + o * E(I1, J1, K1);
-        const T f0 = q * e00 + o * e10;
-        const T f1 = q * e01 + o * e11;
-        x[c] += q * f0 + o * f1;
-    }
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock)
+        prolong_cell<T>(f, cd, e, x, c);
 }
 
 // Mixed-precision outer step (FP64):

@@ -1,0 +1,163 @@
+// The coarse end of a V-cycle in one launch.
+//
+// Below a few thousand cells a level's kernels are far shorter than a launch:
+// the pre-sweeps, residual + restriction, prolongation + correction and
+// post-sweeps of the 16^3, 8^3 ... grids would cost a dozen launches per level
+// for microseconds of work.  Here one workgroup runs all those levels and the
+// exact coarsest-grid solve (the V-cycle's recursion, Sec. 2.2), separating the
+// steps with workgroup barriers instead of kernel boundaries.
+//
+// The iterate and the rhs of every level live in LDS for the whole V-cycle (at
+// most 2 x 4682 values); only the face coefficients, the first level's rhs and
+// the coarsest inverse are read from memory, and only the first level's
+// result is written back.  A Gauss-Seidel half-sweep reads only cells of the
+// other colour, so the sweeps run in place: the same values as the
+// out-of-place sweeps of the per-level kernels.  Every cell value comes from
+// the device functions of the per-level kernels (half_sweep_value,
+// restrict_cell, prolong_value, coarse_apply_block), so both paths give
+// identical results bit for bit.
+#pragma once
+
+#include "mgp_kernels.hpp"
+
+namespace mgp {
+
+constexpr int kTailNT = 1024;      // threads of the one workgroup
+constexpr long kTailCells = 4096;  // largest grid the tail takes (16^3)
+constexpr int kTailLds = 4682;     // cells of a 4096-cell level and all its coarser ones
+// cells per thread whose loads are issued together (FP64: 2, within 128 VGPRs)
+template <typename T>
+constexpr int tail_batch() { return sizeof(T) == 8 ? 2 : 4; }
+constexpr int kTailMaxLevels = 16;
+
+// One level as the tail kernel sees it (a table in device memory, built at
+// setup).  Only the face arrays are used; the level's b, x, t buffers are
+// those of the per-level path, which the tail keeps in LDS instead.
+template <typename T>
+struct TailLevel {
+    const T* bx;
+    const T* by;
+    const T* bz;
+    T* b;
+    T* x;
+    T* t;
+    Dims d;
+    T h2;      // h^2 (sweeps)
+    T inv_h2;  // 1 / h^2 (residual)
+};
+
+// One sweep of x (in LDS) in place: colour c0 (treating x as 0 if zero_in),
+// then the other colour.
+template <typename T>
+__device__ void tail_sweep(const TailLevel<T>& L, const T* b, T* x, int c0, int zero_in)
+{
+    const Dims d = L.d;
+    const int hx = (d.nx + 1) / 2;
+    const int cnt = hx * d.ny * d.nz;
+    constexpr int kTailBatch = tail_batch<T>();
+    for (int h = 0; h < 2; ++h) {
+        const int colour = h == 0 ? c0 : 1 - c0;
+        const int zs = h == 0 ? zero_in : 0;
+        for (int q0 = 0; q0 < cnt; q0 += kTailBatch * kTailNT) {
+            T v[kTailBatch];
+            int c[kTailBatch];
+#pragma unroll
+            for (int u = 0; u < kTailBatch; ++u) {
+                const int q = q0 + u * kTailNT + (int)threadIdx.x;
+                const int m = q % hx, r = q / hx;
+                const int j = r % d.ny, k = r / d.ny;
+                const int i = 2 * m + ((j + k + colour) & 1);
+                c[u] = -1;
+                if (q < cnt && i < d.nx) {
+                    c[u] = (k * d.ny + j) * d.nx + i;
+                    v[u] = half_sweep_value<T>(L.bx, L.by, L.bz, d, L.h2, b, x, zs, i, j, k);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kTailBatch; ++u)
+                if (c[u] >= 0) x[c[u]] = v[u];
+        }
+        __syncthreads();
+    }
+}
+
+// V-cycle from level l0 down to the coarsest level nl-1 and back.  x0: level
+// l0's iterate (read unless zero_init says it counts as 0); b0: its rhs;
+// pre_done: pre-sweeps already run on level l0.  The result goes to x0, or to
+// t0 when the sweeps on level l0 are odd in number (where the per-level path,
+// which sweeps from one buffer into the other, leaves it).
+// Launch: one block of kTailNT threads; levels l0..nl-1 at most kTailCells
+// cells each and kTailLds together, the coarsest at most 64, nl - l0 at most
+// kTailMaxLevels.
+template <typename T>
+__global__ void __launch_bounds__(kTailNT)
+k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double* __restrict__ G,
+              T* x0, T* t0, const T* __restrict__ b0, int pre, int post, int zero_init, int pre_done)
+{
+    __shared__ T xs[kTailLds];  // iterate of each level
+    __shared__ T bs[kTailLds];  // rhs of the levels below l0
+    __shared__ double rs[64];
+    constexpr int kTailBatch = tail_batch<T>();
+    const int tid = (int)threadIdx.x;
+    const int nlv = nl - l0;
+    // level parameters stay in scalar registers (uniform loads from the table)
+    const TailLevel<T>* lv = tab + l0;
+    auto ncell = [&](int k) { return lv[k].d.nx * lv[k].d.ny * lv[k].d.nz; };
+    auto off = [&](int k) {
+        int o = 0;
+        for (int m = 0; m < k; ++m) o += ncell(m);
+        return o;
+    };
+    if (!(zero_init && pre_done == 0))
+        for (int q = tid; q < ncell(0); q += kTailNT) xs[q] = x0[q];
+    __syncthreads();
+
+    for (int k = 0; k < nlv - 1; ++k) {
+        const TailLevel<T>& L = lv[k];
+        T* x = xs + off(k);
+        const T* b = k == 0 ? b0 : bs + off(k);
+        const int zi = k == 0 ? zero_init : 1;
+        const int done = k == 0 ? pre_done : 0;
+        if (zi && pre == 0) {
+            for (int q = tid; q < ncell(k); q += kTailNT) x[q] = (T)0;
+            __syncthreads();
+        }
+        for (int s = 0; s < pre - done; ++s) tail_sweep<T>(L, b, x, 0, zi && done == 0 && s == 0);
+        const Dims cd = lv[k + 1].d;
+        T* bc = bs + off(k + 1);
+        for (int q = tid; q < ncell(k + 1); q += kTailNT) {
+            int I, J, K;
+            cell_of(q, cd, I, J, K);
+            bc[q] = restrict_cell<T>(L.bx, L.by, L.bz, L.d, L.inv_h2, b, x, I, J, K);
+        }
+        __syncthreads();
+    }
+    coarse_apply_block<T>(G, ncell(nlv - 1), bs + off(nlv - 1), xs + off(nlv - 1), rs);
+    __syncthreads();
+    for (int k = nlv - 2; k >= 0; --k) {
+        const TailLevel<T>& L = lv[k];
+        T* x = xs + off(k);
+        const T* e = xs + off(k + 1);
+        const T* b = k == 0 ? b0 : bs + off(k);
+        const Dims cd = lv[k + 1].d;
+        for (int q0 = 0; q0 < ncell(k); q0 += kTailBatch * kTailNT) {
+            T v[kTailBatch];
+#pragma unroll
+            for (int u = 0; u < kTailBatch; ++u) {
+                const int q = q0 + u * kTailNT + tid;
+                if (q < ncell(k)) v[u] = x[q] + prolong_value<T>(L.d, cd, e, q);
+            }
+#pragma unroll
+            for (int u = 0; u < kTailBatch; ++u) {
+                const int q = q0 + u * kTailNT + tid;
+                if (q < ncell(k)) x[q] = v[u];
+            }
+        }
+        __syncthreads();
+        for (int s = 0; s < post; ++s) tail_sweep<T>(L, b, x, 1, 0);
+    }
+    T* out = (((pre - pre_done) + post) & 1) ? t0 : x0;
+    for (int q = tid; q < ncell(0); q += kTailNT) out[q] = xs[q];
+}
+
+}  // namespace mgp

@@ -74,7 +74,9 @@ class Solver:
 
     precision: "fp64" (FP64 V-cycles) or "mixed" (FP32 V-cycles inside an FP64
     defect-correction loop).  zero_guess: solves start from p = 0.  timing:
-    record HIP-event durations of the finest-grid kernels.
+    record HIP-event durations of the finest-grid kernels.  level_launches: one
+    launch per kernel on every level (no single-workgroup launch for the levels
+    of at most 4096 cells; same results).
     """
 
     def __init__(self, beta_x: Optional[torch.Tensor], beta_y: Optional[torch.Tensor] = None,
@@ -82,7 +84,7 @@ class Solver:
                  bc: str = "neumann", precision: str = "fp64", pre: int = 2, post: int = 2,
                  max_cycles: int = 100, coarse_max: int = 4, zero_guess: bool = False,
                  timing: bool = False, stream: Optional[torch.cuda.Stream] = None, method: str = "vcycle",
-                 rho: Optional[torch.Tensor] = None):
+                 rho: Optional[torch.Tensor] = None, level_launches: bool = False):
         self._lib = L.load()
         self._ctx = ctypes.c_void_p(None)
         if bc != "neumann":
@@ -104,7 +106,8 @@ class Solver:
             raise MgError(L.MG_EINVAL, f"method must be 'vcycle' or 'fcg' (got {method!r})")
         self.method = method
         flags = ((L.MG_FLAG_ZERO_GUESS if zero_guess else 0) | (L.MG_FLAG_TIMING if timing else 0)
-                 | (L.MG_FLAG_FCG if method == "fcg" else 0))
+                 | (L.MG_FLAG_FCG if method == "fcg" else 0)
+                 | (L.MG_FLAG_LEVEL_LAUNCHES if level_launches else 0))
         self.opts = L.MgOpts(pre, post, max_cycles, coarse_max, prec, flags)
         self._stream = stream
         self._sh = _stream_handle(stream)

@@ -209,3 +209,48 @@ def test_mixed_zero_guess_without_cycles(density):
     p2, st2 = s.solve(gd, 1e-10, p=torch.zeros_like(gd))
     assert torch.equal(p1, p2) and st1.hist == st2.hist
     s.close()
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8), (16, 16, 16), (8, 16, 32), (12, 8, 16), (32, 32, 32), (96, 96, 96),
+                                  (128, 64, 32), (64, 64, 16)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("method", ["vcycle", "fcg"])
+def test_single_workgroup_levels_match_level_launches(dims, precision, method):
+    """The levels of at most 4096 cells run as one single-workgroup launch by
+    default; with level_launches=True every kernel is its own launch.  Same
+    per-cell arithmetic in the same order: identical solutions and histories."""
+    nx, ny, nz = dims
+    beta = random_beta(dims, 41)
+    h = 1.0 / max(dims)
+    rhs = T(np.random.default_rng(42).standard_normal((nz, ny, nx)))
+    out = []
+    for level_launches in (False, True):
+        with S.Solver(T(beta[0]), T(beta[1]), T(beta[2]), h, precision=precision, zero_guess=True,
+                      method=method, level_launches=level_launches) as s:
+            out.append(s.solve(rhs, 1e-10))
+    (p0, st0), (p1, st1) = out
+    note(f"{dims} {precision} {method}: cycles {st0.cycles}")
+    assert st0.status == S.L.MG_OK and st0.rel_res <= 1e-10
+    assert torch.equal(p0, p1) and st0.hist == st1.hist
+
+
+@pytest.mark.parametrize("pre,post", [(0, 2), (3, 1), (1, 0), (2, 3)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_single_workgroup_levels_sweep_counts(pre, post, precision):
+    """Odd and zero sweep counts: the iterate changes buffers with every sweep
+    and starts from a filled zero when no pre-sweep runs; warm starts too."""
+    dims = (32, 16, 16)
+    nx, ny, nz = dims
+    beta = random_beta(dims, 43)
+    g = np.random.default_rng(44)
+    rhs = T(g.standard_normal((nz, ny, nx)))
+    p_start = g.standard_normal((nz, ny, nx))
+    out = []
+    for level_launches in (False, True):
+        with S.Solver(T(beta[0]), T(beta[1]), T(beta[2]), 1.0 / 32, precision=precision, pre=pre, post=post,
+                      max_cycles=6, level_launches=level_launches) as s:
+            p, st = s.solve(rhs, 1e-14, p=T(p_start), check=False)
+            out.append((p, st))
+    (p0, st0), (p1, st1) = out
+    assert st0.cycles == 6 and st0.hist == st1.hist
+    assert torch.equal(p0, p1)

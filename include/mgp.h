@@ -80,12 +80,15 @@ enum {
                                 Costs three more FP64 cell arrays.  The plain V-cycle
                                 iteration (flag clear) is the method of the paper's solver;
                                 this is a Krylov acceleration of it. */
-    MG_FLAG_LEVEL_LAUNCHES = 8  /* run every level of a V-cycle with one launch per kernel.  By
-                                default the levels of at most 4096 cells that no tiled kernel
+    MG_FLAG_LEVEL_LAUNCHES = 8  /* run every step of a V-cycle as its own launch.  By default
+                                (1) the levels of at most 4096 cells that no tiled kernel
                                 serves (16^3 and below; every level of grids that small) run
-                                in one single-workgroup launch with the same per-cell
-                                arithmetic: identical results, a dozen launches fewer per
-                                level.  For comparison and testing. */
+                                in one single-workgroup launch, and (2) in MG_PREC_MIXED the
+                                first two-sweep launch of a post-smoothing adds the
+                                prolongated coarse correction itself (no separate
+                                prolongation pass).  Both compute every value as the
+                                separate launches do: identical results, fewer launches and
+                                HBM passes.  For comparison and testing. */
 };
 
 /*

@@ -235,14 +235,18 @@ int sweep(mg_ctx* c, int l, const T* b, const T* in, T* out, int order, bool zer
     return MG_OK;
 }
 
-// Two sweeps of one order in one launch (FP32 grids that sweep2_ok accepts).
-int sweep_pair(mg_ctx* c, int l, const float* b, const float* in, float* out, int order, bool zero_in)
+// Two sweeps of one order in one launch (FP32 grids that sweep2_ok accepts);
+// with ec, from in + P ec (the coarse correction of level l + 1 prolongated on
+// the fly).
+int sweep_pair(mg_ctx* c, int l, const float* b, const float* in, float* out, int order, bool zero_in,
+               const float* ec = nullptr)
 {
     Level& L = c->lev[l];
     LevelBufs<float>& B = L.f32;
-    TimedLaunch tl(c, l, MG_K_SWEEP2, 2.0 * (double)L.n * sweep_bytes_per_cell<float>(), true);
+    const double bytes = 2.0 * (double)L.n * sweep_bytes_per_cell<float>() + (ec ? (double)L.n / 8.0 * 4.0 : 0.0);
+    TimedLaunch tl(c, l, MG_K_SWEEP2, bytes, true);
     const hipError_t e = launch_sweep2<float>(B.bx, B.by, B.bz, L.d, (float)(L.h * L.h), b, in, out, order,
-                                              zero_in, c->stream, tl.start(), tl.stop());
+                                              zero_in, c->stream, tl.start(), tl.stop(), ec);
     if (e != hipSuccess) {
         set_err(c, "sweep launch failed: %s", hipGetErrorString(e));
         return MG_EHIP;
@@ -393,6 +397,14 @@ int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init, int pre_d
     T* cx = CB.x;
     T* ct = CB.t;
     TRY(vcycle<T>(c, l + 1, &cx, &ct, CB.b, true));
+    if constexpr (sizeof(T) == 4) {
+        // the first two-sweep launch of the post-smoothing adds the prolongated correction itself
+        if (post >= 2 && sweep2_ok(L.d, sizeof(T)) && !(c->opts.flags & MG_FLAG_LEVEL_LAUNCHES)) {
+            TRY(sweep_pair(c, l, b, *x, *t, 1, false, cx));
+            std::swap(*x, *t);
+            return smooth<T>(c, l, b, x, t, 1, post - 2, false);
+        }
+    }
     TRY(prolong_correct<T>(c, l, cx, *x));
     TRY(smooth<T>(c, l, b, x, t, 1, post, false));
     return MG_OK;

@@ -502,6 +502,18 @@ __global__ void k_residual_restrict(const T* __restrict__ bx, const T* __restric
     }
 }
 
+// One axis of the trilinear prolongation: 3/4 of the parent, 1/4 of the
+// parent's neighbour on the fine cell's side, rounded once (side / 4 is exact,
+// so the explicit fma gives the correctly rounded sum whatever the compiler
+// contracts elsewhere).  Every prolongation path uses it, x first, then y, then
+// z, so they all give the same values.
+template <typename T>
+__device__ __forceinline__ T pro_lerp(T parent, T side)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(0.75f, parent, 0.25f * side);
+    else return __builtin_fma(0.75, parent, 0.25 * side);
+}
+
 // x_fine += trilinear prolongation of the coarse correction e
 template <typename T>
 __device__ inline T prolong_value(const Dims f, const Dims cd, const T* __restrict__ e, long c)
@@ -517,15 +529,14 @@ __device__ inline T prolong_value(const Dims f, const Dims cd, const T* __restri
     K1 = K1 < 0 ? 0 : (K1 > cd.nz - 1 ? cd.nz - 1 : K1);
     const long sy = cd.nx, sz = (long)cd.nx * cd.ny;
     auto E = [&](int a, int bb, int cc) { return e[(long)cc * sz + (long)bb * sy + a]; };
-    // x-direction first, then y, then z: weights 3/4 (parent) and 1/4 (side)
-    const T q = (T)0.75, o = (T)0.25;
-    const T e00 = q * E(I0, J0, K0) + o * E(I1, J0, K0);
-    const T e10 = q * E(I0, J1, K0) + o * E(I1, J1, K0);
-    const T e01 = q * E(I0, J0, K1) + o * E(I1, J0, K1);
-    const T e11 = q * E(I0, J1, K1) + o * E(I1, J1, K1);
-    const T f0 = q * e00 + o * e10;
-    const T f1 = q * e01 + o * e11;
-    return q * f0 + o * f1;
+    // x-direction first, then y, then z
+    const T e00 = pro_lerp(E(I0, J0, K0), E(I1, J0, K0));
+    const T e10 = pro_lerp(E(I0, J1, K0), E(I1, J1, K0));
+    const T e01 = pro_lerp(E(I0, J0, K1), E(I1, J0, K1));
+    const T e11 = pro_lerp(E(I0, J1, K1), E(I1, J1, K1));
+    const T f0 = pro_lerp(e00, e10);
+    const T f1 = pro_lerp(e01, e11);
+    return pro_lerp(f0, f1);
 }
 
 template <typename T>

@@ -56,13 +56,21 @@ struct Sweep2Geom {
     __device__ static int idx(int ex, int ey) { return ey * RS + (ex & 1) * HO + (ex >> 1); }
 };
 
+// Post-smoothing right after a coarse-grid correction can take the correction
+// with it (ec != NULL, coarse dims cd = d / 2): the iterate is then read as
+// in + P ec, P the trilinear prolongation, so the separate prolongation pass
+// (read in, write in) goes away.  The value is the one k_prolong_tiled writes:
+// pro_lerp along x, then y, then z.  Per pair and coarse plane the x- and
+// y-interpolated values (six coarse loads) are formed once and kept while the z
+// march needs them (two planes at a time).
+//
 // Launch contract: nx even and >= 64, every array below 2^31 bytes, grid =
 // ntx * nty * ceil(nz / zc) blocks of Sweep2Geom<TY>::NT threads.
 template <typename T, int TY>
 __global__ void __launch_bounds__(Sweep2Geom<TY>::NT)
 k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
                const T* __restrict__ bb, const T* __restrict__ in, T* __restrict__ out, Dims d, T h2, int c0,
-               int zero_in, int zc, int ntx, int nty)
+               int zero_in, int zc, int ntx, int nty, const T* __restrict__ ec, Dims cd)
 {
     using G = Sweep2Geom<TY>;
     using T2 = typename Vec2<T>::type;
@@ -98,9 +106,56 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     const int le = G::idx(2 * pxi, pyi), lo = G::idx(2 * pxi + 1, pyi);
 
     auto cpl = [&](int z) { return (unsigned)min(max(z, 0), d.nz - 1); };
+    const bool pro = ec != nullptr;
+    const auto r_e = make_rsrc(ec, pro ? (unsigned)((long)cd.nx * cd.ny * cd.nz * sizeof(T)) : 0u);
+    const unsigned cpb = (unsigned)((long)cd.nx * cd.ny * sizeof(T));
+    // x- and y-interpolated correction of coarse plane K for the pair's two cells
+    auto coarse_xy = [&](int K) -> T2 {
+        const int I = gx0 >> 1, J = gy >> 1;
+        const int Im = max(I - 1, 0), Ip = min(I + 1, cd.nx - 1);
+        const int Jn = (gy & 1) ? min(J + 1, cd.ny - 1) : max(J - 1, 0);
+        const unsigned r0 = (unsigned)(J * cd.nx), r1 = (unsigned)(Jn * cd.nx);
+        const unsigned so = (unsigned)K * cpb;
+        auto ld = [&](unsigned row, int i) {
+            return bload1<T>(r_e, inside ? (row + (unsigned)i) * (unsigned)sizeof(T) : kOutside, so);
+        };
+        const T m0 = ld(r0, I), m1 = ld(r1, I);
+        const T a0 = pro_lerp(m0, ld(r0, Im)), a1 = pro_lerp(m0, ld(r0, Ip));
+        const T b0 = pro_lerp(m1, ld(r1, Im)), b1 = pro_lerp(m1, ld(r1, Ip));
+        T2 p;
+        p.x = pro_lerp(a0, b0);
+        p.y = pro_lerp(a1, b1);
+        return p;
+    };
+    // the two coarse planes in hand; a miss replaces the lower one (z only grows)
+    T2 Pa, Pb;
+    Pa.x = Pa.y = Pb.x = Pb.y = (T)0;
+    int Ka = -1, Kb = -1;
+    auto fetch = [&](int K) -> T2 {
+        if (K == Ka) return Pa;
+        if (K == Kb) return Pb;
+        const T2 p = coarse_xy(K);
+        if (Ka < Kb) {
+            Pa = p;
+            Ka = K;
+        } else {
+            Pb = p;
+            Kb = K;
+        }
+        return p;
+    };
     auto load_in = [&](int z) -> T2 {
         const bool zv = !zero_in && z >= 0 && z < d.nz;
-        return bload2<T>(zv ? r_in : r_null, oin, cpl(z) * psz);
+        T2 v = bload2<T>(zv ? r_in : r_null, oin, cpl(z) * psz);
+        if (pro && zv) {
+            // fine plane 2K takes coarse planes K and K-1, plane 2K+1 K and K+1 (clamped)
+            const int K = z >> 1;
+            const int Kn = (z & 1) ? min(K + 1, cd.nz - 1) : max(K - 1, 0);
+            const T2 p = fetch(K), q = fetch(Kn);
+            v.x = v.x + pro_lerp(p.x, q.x);
+            v.y = v.y + pro_lerp(p.y, q.y);
+        }
+        return v;
     };
     // LDS plane of z-step position K (0..6) and plane offset dz from the step's
     // plane s: the loop is unrolled seven times, so slot numbers are constants
@@ -294,14 +349,18 @@ inline bool sweep2_ok(const Dims& d, size_t elem)
 }
 
 // ev0/ev1 (nullable): events that take the kernel's start and end timestamps.
+// ec (nullable): coarse correction to prolongate into `in` on the fly (grid d
+// must then have even extents and ec the d / 2 grid; zero_in false).
 template <typename T>
 hipError_t launch_sweep2(const T* bx, const T* by, const T* bz, Dims d, T h2, const T* b, const T* in, T* out,
-                         int order, bool zero_in, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
+                         int order, bool zero_in, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                         const T* ec = nullptr)
 {
     constexpr int TY = 16;
     const Sweep2Launch g = sweep2_geom<TY>(d);
+    const Dims cd{d.nx / 2, d.ny / 2, d.nz / 2};
     hipExtLaunchKernelGGL(k_sweep2_fused<T, TY>, dim3(g.blocks), dim3(Sweep2Geom<TY>::NT), 0, s, ev0, ev1, 0, bx, by,
-                          bz, b, in, out, d, h2, order == 0 ? 0 : 1, zero_in ? 1 : 0, g.zc, g.ntx, g.nty);
+                          bz, b, in, out, d, h2, order == 0 ? 0 : 1, zero_in ? 1 : 0, g.zc, g.ntx, g.nty, ec, cd);
     return hipGetLastError();
 }
 

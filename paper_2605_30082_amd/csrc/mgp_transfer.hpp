@@ -88,7 +88,6 @@ k_prolong_tiled(Dims f, Dims c, const T* __restrict__ e, T* __restrict__ x, int 
     const int J = y >> 1;
     const int ly0 = J - Y0 + 1;              // parent row
     const int ly1 = ly0 + ((y & 1) ? 1 : -1);  // row neighbour on this cell's side
-    const T q3 = (T)0.75, q1 = (T)0.25;
 
     // prologue
     T v[kProLoads];
@@ -113,27 +112,27 @@ k_prolong_tiled(Dims f, Dims c, const T* __restrict__ e, T* __restrict__ x, int 
         auto xrow = [&](const T* S, int ly, T& c0, T& c1) {
             const T* r = S + ly * kProCX + lx;
             const T m = r[0];
-            c0 = q3 * m + q1 * r[-1];
-            c1 = q3 * m + q1 * r[1];
+            c0 = pro_lerp(m, r[-1]);
+            c1 = pro_lerp(m, r[1]);
         };
         T a0, a1, b0, b1;
         xrow(S0, ly0, a0, a1);
         xrow(S0, ly1, b0, b1);
-        const T p0 = q3 * a0 + q1 * b0, p1 = q3 * a1 + q1 * b1;   // plane K
+        const T p0 = pro_lerp(a0, b0), p1 = pro_lerp(a1, b1);   // plane K
         xrow(Sm, ly0, a0, a1);
         xrow(Sm, ly1, b0, b1);
-        const T m0 = q3 * a0 + q1 * b0, m1 = q3 * a1 + q1 * b1;   // plane K-1 (clamped)
+        const T m0 = pro_lerp(a0, b0), m1 = pro_lerp(a1, b1);   // plane K-1 (clamped)
         xrow(Sp, ly0, a0, a1);
         xrow(Sp, ly1, b0, b1);
-        const T u0 = q3 * a0 + q1 * b0, u1 = q3 * a1 + q1 * b1;   // plane K+1 (clamped)
+        const T u0 = pro_lerp(a0, b0), u1 = pro_lerp(a1, b1);   // plane K+1 (clamped)
         if (mine) {
             const long base = (long)y * f.nx + xp;
             T2 o;
-            o.x = fa.x + (q3 * p0 + q1 * m0);
-            o.y = fa.y + (q3 * p1 + q1 * m1);
+            o.x = fa.x + pro_lerp(p0, m0);
+            o.y = fa.y + pro_lerp(p1, m1);
             *reinterpret_cast<T2*>(x + (long)(2 * K) * fsz + base) = o;
-            o.x = fb.x + (q3 * p0 + q1 * u0);
-            o.y = fb.y + (q3 * p1 + q1 * u1);
+            o.x = fb.x + pro_lerp(p0, u0);
+            o.y = fb.y + pro_lerp(p1, u1);
             *reinterpret_cast<T2*>(x + (long)(2 * K + 1) * fsz + base) = o;
         }
         fa = na;

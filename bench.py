@@ -62,16 +62,16 @@ def kernel_symbol(name, precision, coefficients):
 # drops workload (average over all levels, the unit of the roofline figure), from
 # two rocprofv3 PMC passes over one step: FETCH_SIZE and WRITE_SIZE in KiB, scaled
 # by what the same counters read for a plain 1 GiB device copy (x2.0 and x1.0 on
-# this part).  Valid only for the kernel sources they were taken on: the hash
-# below is recomputed at run time and the figure is dropped (null) once the
-# sources differ.
+# this part).  Valid only for the sources they were taken on (the kernel and the
+# host code that decides its launches): the hash below is recomputed at run time
+# and the figure is dropped (null) once the sources differ.
 TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 16>",
     "n": 512,
-    "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp"],
-    "sha256": "83b164c1beeb8f4be1227be5bc65acf210a32d7e577aa0081bcc2c4c4351d376",
-    "fetch_kib": 408103.564453125,
-    "write_kib": 149763.17823949354,
+    "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
+    "sha256": "3e0207f7bda70e078dc766f069446d920f17eb8d21b5fcef1444aed984222c1a",
+    "fetch_kib": 379836.2515024039,
+    "write_kib": 149760.02338741987,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

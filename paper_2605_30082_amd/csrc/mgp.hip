@@ -75,6 +75,7 @@ struct mg_ctx {
     double setup_ms = 0.0;
     bool valid = false;          // coefficients imported and accepted
     // timing
+    hipEvent_t sync_ev = nullptr;  // marks the scalar copy the mixed loop waits for
     hipEvent_t* ev = nullptr;
     int ev_class[kTimingPairs];
     int ev_level[kTimingPairs];
@@ -173,10 +174,12 @@ struct TimedLaunch {
     }
 };
 
-// after a stream synchronisation: fold recorded event pairs into the totals
-void harvest(mg_ctx* c)
+// after a synchronisation: fold the first `ready` recorded event pairs (all of
+// them by default) into the totals; later pairs move to the front
+void harvest(mg_ctx* c, int ready = -1)
 {
-    for (int t = 0; t < c->ev_used; ++t) {
+    if (ready < 0 || ready > c->ev_used) ready = c->ev_used;
+    for (int t = 0; t < ready; ++t) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->ev[2 * t], c->ev[2 * t + 1]) == hipSuccess) {
             const int k = c->ev_class[t];
@@ -190,7 +193,15 @@ void harvest(mg_ctx* c)
             }
         }
     }
-    c->ev_used = 0;
+    for (int t = ready; t < c->ev_used; ++t) {
+        const int u = t - ready;
+        std::swap(c->ev[2 * u], c->ev[2 * t]);
+        std::swap(c->ev[2 * u + 1], c->ev[2 * t + 1]);
+        c->ev_class[u] = c->ev_class[t];
+        c->ev_level[u] = c->ev_level[t];
+        c->ev_bytes[u] = c->ev_bytes[t];
+    }
+    c->ev_used -= ready;
 }
 
 // --- reductions -----------------------------------------------------------
@@ -199,6 +210,23 @@ int reduce_to(mg_ctx* c, int nparts, int slot)
 {
     k_reduce_final<<<1, kBlock, 0, c->stream>>>(c->partials, nparts, c->scal, slot);
     CHECK_LAUNCH(c);
+    return MG_OK;
+}
+
+// The same in two halves: queue the copy, then (after queueing more work) wait
+// for the copy alone; timing pairs recorded after the copy are kept for later.
+int fetch_scalars_begin(mg_ctx* c, int count, int* ready)
+{
+    HIP_TRY(c, hipMemcpyAsync(c->host_scal, c->scal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipEventRecord(c->sync_ev, c->stream));
+    *ready = c->ev_used;
+    return MG_OK;
+}
+
+int fetch_scalars_end(mg_ctx* c, int ready)
+{
+    HIP_TRY(c, hipEventSynchronize(c->sync_ev));
+    harvest(c, ready);
     return MG_OK;
 }
 
@@ -737,15 +765,40 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
         best = rr;
         if (!std::isfinite(rr)) status = MG_ENONFINITE;
         else if (rr <= tol) status = MG_OK;
+        // While the host waits for a cycle's norm, the next cycle's pre-sweeps are
+        // already queued (they read only the new FP32 residual and write the
+        // correction buffers, never p), so the GPU does not idle through the
+        // round trip.  They are skipped when the norm is expected to meet the
+        // tolerance: rr_k ~ rr_{k-1}^2 / rr_{k-2}, with a margin of 4.
+        const int pre = c->opts.pre;
+        bool queued = false;
+        double rr_before = -1.0;
+        float* ex = F0.f32.x;
+        float* et = F0.f32.t;
         while (status == MG_ENOCONV && cycles < maxc) {
-            float* ex = F0.f32.x;
-            float* et = F0.f32.t;
-            TRY(vcycle<float>(c, 0, &ex, &et, r32, true));
+            if (queued) {
+                TRY(vcycle<float>(c, 0, &ex, &et, r32, true, pre));
+            } else {
+                ex = F0.f32.x;
+                et = F0.f32.t;
+                TRY(vcycle<float>(c, 0, &ex, &et, r32, true));
+            }
+            queued = false;
             TRY(outer_update(c, p_zero ? nullptr : cur, ex, other, r32, 2));
             p_zero = false;
             std::swap(cur, other);
             ++cycles;
-            TRY(fetch_scalars(c, 3));
+            int ready = 0;
+            TRY(fetch_scalars_begin(c, 3, &ready));
+            const double expect = rr_before > 0.0 ? rr * (rr / rr_before) : HUGE_VAL;
+            if (pre > 0 && cycles < maxc && expect > 4.0 * tol) {
+                ex = F0.f32.x;
+                et = F0.f32.t;
+                TRY(smooth<float>(c, 0, r32, &ex, &et, 0, pre, true));
+                queued = true;
+            }
+            TRY(fetch_scalars_end(c, ready));
+            rr_before = rr;
             rr = std::sqrt(c->host_scal[2]) / bnorm;
             if (st && cycles < MG_HIST_MAX) st->hist[cycles] = rr;
             if (!std::isfinite(rr)) { status = MG_ENONFINITE; break; }
@@ -793,6 +846,7 @@ void free_ctx(mg_ctx* c)
             if (c->ev[t]) (void)hipEventDestroy(c->ev[t]);
         delete[] c->ev;
     }
+    if (c->sync_ev) (void)hipEventDestroy(c->sync_ev);
     if (c->arena) (void)hipFree(c->arena);
     if (c->host_scal) (void)hipHostFree(c->host_scal);
     delete c;
@@ -1061,6 +1115,10 @@ int setup_ctx(mg_ctx** out, const double* beta_x, const double* beta_y, const do
         hipSuccess) {
         set_err(c, "pinned host allocation failed");
         return fail(MG_ENOMEM);
+    }
+    if (hipEventCreateWithFlags(&c->sync_ev, hipEventDisableTiming) != hipSuccess) {
+        set_err(c, "hipEventCreate failed");
+        return fail(MG_EHIP);
     }
     if (o.flags & MG_FLAG_TIMING) {
         c->ev = new (std::nothrow) hipEvent_t[2 * kTimingPairs]();

@@ -598,22 +598,52 @@ int fcg_loop(mg_ctx* c, double* x, double bnorm, double tol, bool zero_guess, mg
     if (!std::isfinite(rr)) status = MG_ENONFINITE;
     else if (rr <= tol) status = MG_OK;
     double best = rr, dq_prev = 0.0;
+    // as in the mixed V-cycle loop: the next preconditioner's pre-sweeps are
+    // queued while the host waits for the norm, unless it is expected to converge
+    const int pre = c->opts.pre;
+    bool queued = false;
+    double rr_before = -1.0;
+    float* zx32 = F.f32.x;
+    float* zt32 = F.f32.t;
+    double* zx64 = F.f64.x;
+    double* zt64 = F.f64.t;
     while (status == MG_ENOCONV && it < c->opts.max_cycles) {
         const bool first = it == 0;
         if (c->mixed) {
-            float* zx = F.f32.x;
-            float* zt = F.f32.t;
-            TRY(vcycle<float>(c, 0, &zx, &zt, r32, true));
-            TRY(fcg_step<float>(c, zx, x, r32, first, dq_prev));
+            if (!queued) {
+                zx32 = F.f32.x;
+                zt32 = F.f32.t;
+            }
+            TRY(vcycle<float>(c, 0, &zx32, &zt32, r32, true, queued ? pre : 0));
+            TRY(fcg_step<float>(c, zx32, x, r32, first, dq_prev));
         } else {
-            double* zx = F.f64.x;
-            double* zt = F.f64.t;
-            TRY(vcycle<double>(c, 0, &zx, &zt, c->fr, true));
-            TRY(fcg_step<double>(c, zx, x, nullptr, first, dq_prev));
+            if (!queued) {
+                zx64 = F.f64.x;
+                zt64 = F.f64.t;
+            }
+            TRY(vcycle<double>(c, 0, &zx64, &zt64, c->fr, true, queued ? pre : 0));
+            TRY(fcg_step<double>(c, zx64, x, nullptr, first, dq_prev));
         }
-        TRY(fetch_scalars(c, kSlotDR + 1));
+        queued = false;
+        int ready = 0;
+        TRY(fetch_scalars_begin(c, kSlotDR + 1, &ready));
+        const double expect = rr_before > 0.0 ? rr * (rr / rr_before) : HUGE_VAL;
+        if (pre > 0 && it + 1 < c->opts.max_cycles && expect > 4.0 * tol) {
+            if (c->mixed) {
+                zx32 = F.f32.x;
+                zt32 = F.f32.t;
+                TRY(smooth<float>(c, 0, r32, &zx32, &zt32, 0, pre, true));
+            } else {
+                zx64 = F.f64.x;
+                zt64 = F.f64.t;
+                TRY(smooth<double>(c, 0, c->fr, &zx64, &zt64, 0, pre, true));
+            }
+            queued = true;
+        }
+        TRY(fetch_scalars_end(c, ready));
         dq_prev = c->host_scal[kSlotDQ];
         ++it;
+        rr_before = rr;
         rr = std::sqrt(c->host_scal[kSlotRR]) / bnorm;
         if (st && it < MG_HIST_MAX) st->hist[it] = rr;
         if (!std::isfinite(rr)) { status = MG_ENONFINITE; break; }

@@ -69,9 +69,9 @@ TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "3e0207f7bda70e078dc766f069446d920f17eb8d21b5fcef1444aed984222c1a",
-    "fetch_kib": 379836.2515024039,
-    "write_kib": 149760.02338741987,
+    "sha256": "37d84b0af2f074567ffab43d543b2dbf4fb19e8b8a2e266ffdf36fbafc88fe84",
+    "fetch_kib": 379699.1510416667,
+    "write_kib": 149760.0294220753,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

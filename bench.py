@@ -42,7 +42,7 @@ SWEEPS_PER_LAUNCH = {"sweep": 1, "sweep2": 2}
 KERNEL_SYMBOLS = {
     ("sweep", "mixed"): "mgp::k_sweep_fused<float, 8, false>",
     ("sweep", "fp64"): "mgp::k_sweep_fused<double, 16, false>",
-    ("sweep2", "mixed"): "mgp::k_sweep2_fused<float, 16>",
+    ("sweep2", "mixed"): "mgp::k_sweep2_fused<float, 64, 16>",
     ("residual_restrict", "mixed"): "mgp::k_resid<float, 1, false>",
     ("residual_restrict", "fp64"): "mgp::k_resid<double, 1, {rho}>",
     ("prolong_correct", "mixed"): "mgp::k_prolong_tiled<float>",
@@ -66,7 +66,7 @@ def kernel_symbol(name, precision, coefficients):
 # host code that decides its launches): the hash below is recomputed at run time
 # and the figure is dropped (null) once the sources differ.
 TRAFFIC = {
-    "kernel": "mgp::k_sweep2_fused<float, 16>",
+    "kernel": "mgp::k_sweep2_fused<float, 64, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
     "sha256": "37d84b0af2f074567ffab43d543b2dbf4fb19e8b8a2e266ffdf36fbafc88fe84",

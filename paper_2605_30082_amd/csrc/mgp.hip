@@ -274,7 +274,7 @@ int sweep_pair(mg_ctx* c, int l, const float* b, const float* in, float* out, in
     // algorithmic bytes of the work done: two sweeps, plus (ec) the prolongation + correction pass it replaces
     const double bytes = 2.0 * (double)L.n * sweep_bytes_per_cell<float>() +
                          (ec ? (double)L.n * (2.0 + 1.0 / 8.0) * sizeof(float) : 0.0);
-    TimedLaunch tl(c, l, MG_K_SWEEP2, bytes, true);
+    TimedLaunch tl(c, l, MG_K_SWEEP2, bytes, sweep2_wide(L.d));
     const hipError_t e = launch_sweep2<float>(B.bx, B.by, B.bz, L.d, (float)(L.h * L.h), b, in, out, order,
                                               zero_in, c->stream, tl.start(), tl.stop(), ec);
     if (e != hipSuccess) {

@@ -5,7 +5,7 @@
 //   B2: B-cells from A2.    out = (A2 on A-cells, B2 on B-cells).
 // A half-sweep of a cell reads only its six face neighbours, which have the
 // other colour, so a stage on plane z needs the previous stage on planes
-// z-1, z, z+1.  A block that owns a 64 x TY tile of (x, y) marches a chunk of
+// z-1, z, z+1.  A block that owns a TX x TY tile of (x, y) marches a chunk of
 // z with the stages staggered in z, per step s (two LDS barriers):
 //   phase 1: A1 on plane s   (tile + 3-cell ring)  and  A2 on plane s-3 (tile + 1-cell ring)
 //   phase 2: B1 on plane s-1 (tile + 2-cell ring)  and  B2 on plane s-4 (tile)
@@ -20,7 +20,7 @@
 // A-cells of s-2 before A2 overwrites them in the same step).
 //
 // Each thread owns one pair of x-adjacent cells of the tile + 4-cell ring
-// (36 pairs per row, TY + 8 rows): in every plane one cell of the pair is an
+// (TX / 2 + 4 pairs per row, TY + 8 rows): in every plane one cell of the pair is an
 // A-cell and the other a B-cell.  The coefficients of the pair's cells are
 // loaded once per plane, two steps before first full use, and kept in
 // registers for the steps during which the four stages visit that plane.  The
@@ -34,21 +34,23 @@
 
 namespace mgp {
 
-template <int TY>
+template <int TX_, int TY>
 struct Sweep2Geom {
-    static constexpr int TX = 64;              // tile width (cells)
+    static constexpr int TX = TX_;             // tile width (cells): 64, or 32 for 32-wide grids
     static constexpr int EX = TX + 8;          // LDS plane: x0-4 .. x0+TX+3
     static constexpr int EY = TY + 8;          //            y0-4 .. y0+TY+3
     static constexpr int HX = EX / 2;          // pairs per row
     static constexpr int NP = HX * EY;         // pairs per plane = working threads
     static constexpr int NT = (NP + 63) / 64 * 64;
-    // LDS row stride and offset of a row's odd-x cells.  A wave spans rows of 36
-    // pairs; with RS +- HO = 36 (mod 32), the next row's cells of one colour
-    // start in the bank after the previous row's last, and 2 RS = 8 (mod 64):
-    // fewer bank conflicts than the packed 72 / 36 layout (measured: 0.864
-    // against 0.879 ms per 512^3 launch)
-    static constexpr int RS = 100;
-    static constexpr int HO = 64;
+    // LDS row stride and offset of a row's odd-x cells.  64-wide tiles: a wave
+    // spans rows of 36 pairs; with RS +- HO = 36 (mod 32), the next row's cells
+    // of one colour start in the bank after the previous row's last, and
+    // 2 RS = 8 (mod 64): fewer bank conflicts than the packed 72 / 36 layout
+    // (measured: 0.864 against 0.879 ms per 512^3 launch).  32-wide tiles (rows
+    // of 20 pairs): the same rule, RS - HO = 20 + 4.
+    static constexpr int RS = TX == 64 ? 100 : 56;
+    static constexpr int HO = TX == 64 ? 64 : 32;
+    static_assert(RS >= HO + HX, "a row's odd-x cells must not reach the next row");
     static constexpr int PLANE = RS * EY;
     static constexpr int SLOTS = 7;         // planes s-5 .. s+1 of step s
     // LDS position of plane coordinates (ex, ey): each row keeps its even-x
@@ -64,15 +66,15 @@ struct Sweep2Geom {
 // y-interpolated values (six coarse loads) are formed once and kept while the z
 // march needs them (two planes at a time).
 //
-// Launch contract: nx even and >= 64, every array below 2^31 bytes, grid =
-// ntx * nty * ceil(nz / zc) blocks of Sweep2Geom<TY>::NT threads.
-template <typename T, int TY>
-__global__ void __launch_bounds__(Sweep2Geom<TY>::NT)
+// Launch contract: nx even and >= TX, ny >= TY, every array below 2^31 bytes,
+// grid = ntx * nty * ceil(nz / zc) blocks of Sweep2Geom<TX, TY>::NT threads.
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((Sweep2Geom<TX, TY>::NT))
 k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
                const T* __restrict__ bb, const T* __restrict__ in, T* __restrict__ out, Dims d, T h2, int c0,
                int zero_in, int zc, int ntx, int nty, const T* __restrict__ ec, Dims cd)
 {
-    using G = Sweep2Geom<TY>;
+    using G = Sweep2Geom<TX, TY>;
     using T2 = typename Vec2<T>::type;
     __shared__ T slot[G::SLOTS * G::PLANE];
     const int nb = (int)gridDim.x, bid = (int)blockIdx.x;
@@ -324,11 +326,11 @@ struct Sweep2Launch {
     int ntx, nty, zc, blocks;
 };
 
-template <int TY>
+template <int TX, int TY>
 inline Sweep2Launch sweep2_geom(const Dims& d)
 {
     Sweep2Launch g;
-    g.ntx = (d.nx + 63) / 64;
+    g.ntx = (d.nx + TX - 1) / TX;
     g.nty = (d.ny + TY - 1) / TY;
     const int tiles = g.ntx * g.nty;
     int nzc = (256 + tiles - 1) / tiles;
@@ -340,13 +342,16 @@ inline Sweep2Launch sweep2_geom(const Dims& d)
     return g;
 }
 
-// Grids the two-sweep kernel serves: at least 64 cells wide (even) and 16
-// rows, arrays below 2^31 bytes.
+// Grids the two-sweep kernel serves: at least 32 cells wide (even; 64-wide
+// tiles from 64 cells on) and 16 rows, arrays below 2^31 bytes.
 inline bool sweep2_ok(const Dims& d, size_t elem)
 {
     const long big = n_fx(d) > n_fz(d) ? n_fx(d) : n_fz(d);
-    return elem == 4 && d.nx >= 64 && (d.nx % 2) == 0 && d.ny >= 16 && big * (long)elem < (1L << 31);
+    return elem == 4 && d.nx >= 32 && (d.nx % 2) == 0 && d.ny >= 16 && big * (long)elem < (1L << 31);
 }
+
+// the launches with 64-wide tiles (the timed ones)
+inline bool sweep2_wide(const Dims& d) { return d.nx >= 64; }
 
 // ev0/ev1 (nullable): events that take the kernel's start and end timestamps.
 // ec (nullable): coarse correction to prolongate into `in` on the fly (grid d
@@ -357,10 +362,17 @@ hipError_t launch_sweep2(const T* bx, const T* by, const T* bz, Dims d, T h2, co
                          const T* ec = nullptr)
 {
     constexpr int TY = 16;
-    const Sweep2Launch g = sweep2_geom<TY>(d);
     const Dims cd{d.nx / 2, d.ny / 2, d.nz / 2};
-    hipExtLaunchKernelGGL(k_sweep2_fused<T, TY>, dim3(g.blocks), dim3(Sweep2Geom<TY>::NT), 0, s, ev0, ev1, 0, bx, by,
-                          bz, b, in, out, d, h2, order == 0 ? 0 : 1, zero_in ? 1 : 0, g.zc, g.ntx, g.nty, ec, cd);
+    const int c0 = order == 0 ? 0 : 1, zi = zero_in ? 1 : 0;
+    if (sweep2_wide(d)) {
+        const Sweep2Launch g = sweep2_geom<64, TY>(d);
+        hipExtLaunchKernelGGL(k_sweep2_fused<T, 64, TY>, dim3(g.blocks), dim3(Sweep2Geom<64, TY>::NT), 0, s, ev0, ev1,
+                              0, bx, by, bz, b, in, out, d, h2, c0, zi, g.zc, g.ntx, g.nty, ec, cd);
+    } else {
+        const Sweep2Launch g = sweep2_geom<32, TY>(d);
+        hipExtLaunchKernelGGL(k_sweep2_fused<T, 32, TY>, dim3(g.blocks), dim3(Sweep2Geom<32, TY>::NT), 0, s, ev0, ev1,
+                              0, bx, by, bz, b, in, out, d, h2, c0, zi, g.zc, g.ntx, g.nty, ec, cd);
+    }
     return hipGetLastError();
 }
 

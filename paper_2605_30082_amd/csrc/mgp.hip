@@ -380,8 +380,11 @@ template <typename T>
 int vcycle_tail(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init, int pre_done)
 {
     const int pre = c->opts.pre, post = c->opts.post;
+    long faces = 0;
+    for (int k = l; k < c->nlev - 1; ++k) faces += n_fx(c->lev[k].d) + n_fy(c->lev[k].d) + n_fz(c->lev[k].d);
+    const int faces_lds = sizeof(T) == 4 && faces <= kTailFaceLds ? 1 : 0;
     k_vcycle_tail<T><<<1, kTailNT, 0, c->stream>>>(tail_tab<T>(c), l, c->nlev, c->G, *x, *t, b, pre, post,
-                                                   zero_init ? 1 : 0, pre_done);
+                                                   zero_init ? 1 : 0, pre_done, faces_lds);
     CHECK_LAUNCH(c);
     if (((pre - pre_done) + post) & 1) std::swap(*x, *t);
     return MG_OK;

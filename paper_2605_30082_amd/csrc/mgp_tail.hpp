@@ -8,9 +8,9 @@
 // steps with workgroup barriers instead of kernel boundaries.
 //
 // The iterate and the rhs of every level live in LDS for the whole V-cycle (at
-// most 2 x 4682 values); only the face coefficients, the first level's rhs and
-// the coarsest inverse are read from memory, and only the first level's
-// result is written back.  A Gauss-Seidel half-sweep reads only cells of the
+// most 2 x 4682 values), in FP32 the face coefficients too (copied in at the
+// start); otherwise only the first level's rhs and the coarsest inverse are
+// read from memory, and only the first level's result is written back.  A Gauss-Seidel half-sweep reads only cells of the
 // other colour, so the sweeps run in place: the same values as the
 // out-of-place sweeps of the per-level kernels.  Every cell value comes from
 // the device functions of the per-level kernels (half_sweep_value,
@@ -29,6 +29,7 @@ constexpr int kTailLds = 4682;     // cells of a 4096-cell level and all its coa
 template <typename T>
 constexpr int tail_batch() { return sizeof(T) == 8 ? 2 : 4; }
 constexpr int kTailMaxLevels = 16;
+constexpr int kTailFaceLds = 24576;  // FP32 face coefficients kept in LDS (96 KB)
 
 // One level as the tail kernel sees it (a table in device memory, built at
 // setup).  Only the face arrays are used; the level's b, x, t buffers are
@@ -47,11 +48,11 @@ struct TailLevel {
 };
 
 // One sweep of x (in LDS) in place: colour c0 (treating x as 0 if zero_in),
-// then the other colour.
+// then the other colour.  fx, fy, fz: the level's faces (LDS or memory).
 template <typename T>
-__device__ void tail_sweep(const TailLevel<T>& L, const T* b, T* x, int c0, int zero_in)
+__device__ void tail_sweep(const T* fx, const T* fy, const T* fz, const Dims d, T h2, const T* b, T* x, int c0,
+                           int zero_in)
 {
-    const Dims d = L.d;
     const int hx = (d.nx + 1) / 2;
     const int cnt = hx * d.ny * d.nz;
     constexpr int kTailBatch = tail_batch<T>();
@@ -70,7 +71,7 @@ __device__ void tail_sweep(const TailLevel<T>& L, const T* b, T* x, int c0, int 
                 c[u] = -1;
                 if (q < cnt && i < d.nx) {
                     c[u] = (k * d.ny + j) * d.nx + i;
-                    v[u] = half_sweep_value<T>(L.bx, L.by, L.bz, d, L.h2, b, x, zs, i, j, k);
+                    v[u] = half_sweep_value<T>(fx, fy, fz, d, h2, b, x, zs, i, j, k);
                 }
             }
 #pragma unroll
@@ -86,16 +87,20 @@ __device__ void tail_sweep(const TailLevel<T>& L, const T* b, T* x, int c0, int 
 // pre_done: pre-sweeps already run on level l0.  The result goes to x0, or to
 // t0 when the sweeps on level l0 are odd in number (where the per-level path,
 // which sweeps from one buffer into the other, leaves it).
+// faces_lds (FP32 only): the face coefficients of levels l0..nl-2 are copied
+// to LDS first (at most kTailFaceLds values together), so that no step after
+// the start reads memory except the first level's rhs and the coarsest inverse.
 // Launch: one block of kTailNT threads; levels l0..nl-1 at most kTailCells
 // cells each and kTailLds together, the coarsest at most 64, nl - l0 at most
 // kTailMaxLevels.
 template <typename T>
 __global__ void __launch_bounds__(kTailNT)
 k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double* __restrict__ G,
-              T* x0, T* t0, const T* __restrict__ b0, int pre, int post, int zero_init, int pre_done)
+              T* x0, T* t0, const T* __restrict__ b0, int pre, int post, int zero_init, int pre_done, int faces_lds)
 {
     __shared__ T xs[kTailLds];  // iterate of each level
     __shared__ T bs[kTailLds];  // rhs of the levels below l0
+    __shared__ T fs[sizeof(T) == 4 ? kTailFaceLds : 1];  // faces of the swept levels (FP32)
     __shared__ double rs[64];
     constexpr int kTailBatch = tail_batch<T>();
     const int tid = (int)threadIdx.x;
@@ -108,12 +113,44 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
         for (int m = 0; m < k; ++m) o += ncell(m);
         return o;
     };
+    auto nfaces = [&](int k) { return (int)(n_fx(lv[k].d) + n_fy(lv[k].d) + n_fz(lv[k].d)); };
+    auto foff = [&](int k) {
+        int o = 0;
+        for (int m = 0; m < k; ++m) o += nfaces(m);
+        return o;
+    };
     if (!(zero_init && pre_done == 0))
         for (int q = tid; q < ncell(0); q += kTailNT) xs[q] = x0[q];
+    if constexpr (sizeof(T) == 4) {
+        if (faces_lds) {
+            for (int k = 0; k < nlv - 1; ++k) {
+                T* F = fs + foff(k);
+                const int a = (int)n_fx(lv[k].d), c = (int)n_fy(lv[k].d), e = (int)n_fz(lv[k].d);
+                for (int q = tid; q < a; q += kTailNT) F[q] = lv[k].bx[q];
+                for (int q = tid; q < c; q += kTailNT) F[a + q] = lv[k].by[q];
+                for (int q = tid; q < e; q += kTailNT) F[a + c + q] = lv[k].bz[q];
+            }
+        }
+    }
     __syncthreads();
+    // the faces of level k, from LDS or from memory
+    auto faces = [&](int k, const T*& fx, const T*& fy, const T*& fz) {
+        fx = lv[k].bx;
+        fy = lv[k].by;
+        fz = lv[k].bz;
+        if constexpr (sizeof(T) == 4) {
+            if (faces_lds) {
+                fx = fs + foff(k);
+                fy = fx + n_fx(lv[k].d);
+                fz = fy + n_fy(lv[k].d);
+            }
+        }
+    };
 
     for (int k = 0; k < nlv - 1; ++k) {
         const TailLevel<T>& L = lv[k];
+        const T *fx, *fy, *fz;
+        faces(k, fx, fy, fz);
         T* x = xs + off(k);
         const T* b = k == 0 ? b0 : bs + off(k);
         const int zi = k == 0 ? zero_init : 1;
@@ -122,13 +159,13 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
             for (int q = tid; q < ncell(k); q += kTailNT) x[q] = (T)0;
             __syncthreads();
         }
-        for (int s = 0; s < pre - done; ++s) tail_sweep<T>(L, b, x, 0, zi && done == 0 && s == 0);
+        for (int s = 0; s < pre - done; ++s) tail_sweep<T>(fx, fy, fz, L.d, L.h2, b, x, 0, zi && done == 0 && s == 0);
         const Dims cd = lv[k + 1].d;
         T* bc = bs + off(k + 1);
         for (int q = tid; q < ncell(k + 1); q += kTailNT) {
             int I, J, K;
             cell_of(q, cd, I, J, K);
-            bc[q] = restrict_cell<T>(L.bx, L.by, L.bz, L.d, L.inv_h2, b, x, I, J, K);
+            bc[q] = restrict_cell<T>(fx, fy, fz, L.d, L.inv_h2, b, x, I, J, K);
         }
         __syncthreads();
     }
@@ -136,6 +173,8 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
     __syncthreads();
     for (int k = nlv - 2; k >= 0; --k) {
         const TailLevel<T>& L = lv[k];
+        const T *fx, *fy, *fz;
+        faces(k, fx, fy, fz);
         T* x = xs + off(k);
         const T* e = xs + off(k + 1);
         const T* b = k == 0 ? b0 : bs + off(k);
@@ -154,7 +193,7 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
             }
         }
         __syncthreads();
-        for (int s = 0; s < post; ++s) tail_sweep<T>(L, b, x, 1, 0);
+        for (int s = 0; s < post; ++s) tail_sweep<T>(fx, fy, fz, L.d, L.h2, b, x, 1, 0);
     }
     T* out = (((pre - pre_done) + post) & 1) ? t0 : x0;
     for (int q = tid; q < ncell(0); q += kTailNT) out[q] = xs[q];

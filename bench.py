@@ -69,9 +69,9 @@ TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 64, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "37d84b0af2f074567ffab43d543b2dbf4fb19e8b8a2e266ffdf36fbafc88fe84",
-    "fetch_kib": 379699.1510416667,
-    "write_kib": 149760.0294220753,
+    "sha256": "dc2889d950f9c4695032d5fe1b59037d56f1edb431574356b35258a695ca547e",
+    "fetch_kib": 379771.46188902244,
+    "write_kib": 149760.02689302884,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

@@ -971,10 +971,8 @@ int upload_tail(mg_ctx* c)
     for (int l = 0; l < c->nlev; ++l) {
         const Level& L = c->lev[l];
         const double h2 = L.h * L.h;
-        c->tail64_h[l] = {L.f64.bx, L.f64.by, L.f64.bz, L.f64.b, L.f64.x, L.f64.t, L.d, h2, 1.0 / h2};
-        if (c->mixed)
-            c->tail32_h[l] = {L.f32.bx, L.f32.by, L.f32.bz, L.f32.b, L.f32.x, L.f32.t, L.d, (float)h2,
-                              (float)(1.0 / h2)};
+        c->tail64_h[l] = {L.f64.bx, L.f64.by, L.f64.bz, L.d, h2, 1.0 / h2};
+        if (c->mixed) c->tail32_h[l] = {L.f32.bx, L.f32.by, L.f32.bz, L.d, (float)h2, (float)(1.0 / h2)};
     }
     HIP_TRY(c, hipMemcpyAsync(c->tail64, c->tail64_h, sizeof(c->tail64_h), hipMemcpyHostToDevice, c->stream));
     if (c->mixed)

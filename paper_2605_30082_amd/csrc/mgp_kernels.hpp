@@ -361,19 +361,37 @@ __global__ void k_coarse_apply(const double* __restrict__ G, int n, const T* __r
 // stencil helpers
 // ---------------------------------------------------------------------------
 
-// diag = sum of coupled face coefficients, off = sum beta_f * x_neighbour
-template <typename T, typename X>
-__device__ inline void stencil(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
-                               const X* x, const Dims d, int i, int j, int k, long c, T& diag, T& off)
+// Face and cell indices in an index type I: long in general, int where a
+// level is known to be small (the single-workgroup launch); same values.
+template <typename I>
+__device__ inline I fx_at(const Dims& d, int x, int y, int z)
 {
-    const long sy = d.nx, sz = (long)d.nx * d.ny;
+    return ((I)z * d.ny + y) * (d.nx + 2) + x;
+}
+template <typename I>
+__device__ inline I fy_at(const Dims& d, int x, int y, int z)
+{
+    return ((I)z * (d.ny + 1) + y) * d.nx + x;
+}
+template <typename I>
+__device__ inline I fz_at(const Dims& d, int x, int y, int z)
+{
+    return ((I)z * d.ny + y) * d.nx + x;
+}
+
+// diag = sum of coupled face coefficients, off = sum beta_f * x_neighbour
+template <typename T, typename X, typename I = long>
+__device__ inline void stencil(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
+                               const X* x, const Dims d, int i, int j, int k, I c, T& diag, T& off)
+{
+    const I sy = d.nx, sz = (I)d.nx * d.ny;
     T dg = 0, of = 0, f;
-    if (i > 0)        { f = bx[fx_index(d, i, j, k)];     dg += f; of += f * (T)x[c - 1]; }
-    if (i < d.nx - 1) { f = bx[fx_index(d, i + 1, j, k)]; dg += f; of += f * (T)x[c + 1]; }
-    if (j > 0)        { f = by[fy_index(d, i, j, k)];     dg += f; of += f * (T)x[c - sy]; }
-    if (j < d.ny - 1) { f = by[fy_index(d, i, j + 1, k)]; dg += f; of += f * (T)x[c + sy]; }
-    if (k > 0)        { f = bz[fz_index(d, i, j, k)];     dg += f; of += f * (T)x[c - sz]; }
-    if (k < d.nz - 1) { f = bz[fz_index(d, i, j, k + 1)]; dg += f; of += f * (T)x[c + sz]; }
+    if (i > 0)        { f = bx[fx_at<I>(d, i, j, k)];     dg += f; of += f * (T)x[c - 1]; }
+    if (i < d.nx - 1) { f = bx[fx_at<I>(d, i + 1, j, k)]; dg += f; of += f * (T)x[c + 1]; }
+    if (j > 0)        { f = by[fy_at<I>(d, i, j, k)];     dg += f; of += f * (T)x[c - sy]; }
+    if (j < d.ny - 1) { f = by[fy_at<I>(d, i, j + 1, k)]; dg += f; of += f * (T)x[c + sy]; }
+    if (k > 0)        { f = bz[fz_at<I>(d, i, j, k)];     dg += f; of += f * (T)x[c - sz]; }
+    if (k < d.nz - 1) { f = bz[fz_at<I>(d, i, j, k + 1)]; dg += f; of += f * (T)x[c + sz]; }
     diag = dg;
     off = of;
 }
@@ -423,24 +441,24 @@ __global__ void k_residual_norm(const double* __restrict__ bx, const double* __r
 // src holds the other colour (it may alias dst).  With zero_src the other
 // colour is taken as 0.  A cell with no coupled face copies its old value.
 // Launch: grid (ceil(ceil(nx/2)/64), ceil(ny/4), nz), block (64, 4).
-template <typename T>
+template <typename T, typename I = long>
 __device__ inline T half_sweep_value(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
                                      const Dims d, T h2, const T* __restrict__ b, const T* src, int zero_src, int i,
                                      int j, int k)
 {
-    const long c = ((long)k * d.ny + j) * d.nx + i;
+    const I c = ((I)k * d.ny + j) * d.nx + i;
     T dg, of;
     if (zero_src) {
         dg = 0;
-        if (i > 0) dg += bx[fx_index(d, i, j, k)];
-        if (i < d.nx - 1) dg += bx[fx_index(d, i + 1, j, k)];
-        if (j > 0) dg += by[fy_index(d, i, j, k)];
-        if (j < d.ny - 1) dg += by[fy_index(d, i, j + 1, k)];
-        if (k > 0) dg += bz[fz_index(d, i, j, k)];
-        if (k < d.nz - 1) dg += bz[fz_index(d, i, j, k + 1)];
+        if (i > 0) dg += bx[fx_at<I>(d, i, j, k)];
+        if (i < d.nx - 1) dg += bx[fx_at<I>(d, i + 1, j, k)];
+        if (j > 0) dg += by[fy_at<I>(d, i, j, k)];
+        if (j < d.ny - 1) dg += by[fy_at<I>(d, i, j + 1, k)];
+        if (k > 0) dg += bz[fz_at<I>(d, i, j, k)];
+        if (k < d.nz - 1) dg += bz[fz_at<I>(d, i, j, k + 1)];
         of = 0;
     } else {
-        stencil(bx, by, bz, src, d, i, j, k, c, dg, of);
+        stencil<T, T, I>(bx, by, bz, src, d, i, j, k, c, dg, of);
     }
     T v;
     if (dg > (T)0) v = (of - h2 * b[c]) / dg;
@@ -471,7 +489,7 @@ __global__ void k_half_sweep(const T* __restrict__ bx, const T* __restrict__ by,
 }
 
 // b_coarse = mean over the 8 children of (b - L x) (fine dims f, coarse dims c)
-template <typename T>
+template <typename T, typename IX = long>
 __device__ inline T restrict_cell(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
                                   const Dims f, T inv_h2, const T* __restrict__ b, const T* __restrict__ x, int I,
                                   int J, int K)
@@ -481,9 +499,9 @@ __device__ inline T restrict_cell(const T* __restrict__ bx, const T* __restrict_
         for (int cy = 0; cy < 2; ++cy)
             for (int cx = 0; cx < 2; ++cx) {
                 const int i = 2 * I + cx, j = 2 * J + cy, k = 2 * K + cz;
-                const long c = ((long)k * f.ny + j) * f.nx + i;
+                const IX c = ((IX)k * f.ny + j) * f.nx + i;
                 T dg, of;
-                stencil(bx, by, bz, x, f, i, j, k, c, dg, of);
+                stencil<T, T, IX>(bx, by, bz, x, f, i, j, k, c, dg, of);
                 s += b[c] - (of - dg * x[c]) * inv_h2;
             }
     return s * (T)0.125;
@@ -515,8 +533,8 @@ __device__ __forceinline__ T pro_lerp(T parent, T side)
 }
 
 // x_fine += trilinear prolongation of the coarse correction e
-template <typename T>
-__device__ inline T prolong_value(const Dims f, const Dims cd, const T* __restrict__ e, long c)
+template <typename T, typename IX = long>
+__device__ inline T prolong_value(const Dims f, const Dims cd, const T* __restrict__ e, IX c)
 {
     int i, j, k;
     cell_of(c, f, i, j, k);
@@ -527,8 +545,8 @@ __device__ inline T prolong_value(const Dims f, const Dims cd, const T* __restri
     I1 = I1 < 0 ? 0 : (I1 > cd.nx - 1 ? cd.nx - 1 : I1);
     J1 = J1 < 0 ? 0 : (J1 > cd.ny - 1 ? cd.ny - 1 : J1);
     K1 = K1 < 0 ? 0 : (K1 > cd.nz - 1 ? cd.nz - 1 : K1);
-    const long sy = cd.nx, sz = (long)cd.nx * cd.ny;
-    auto E = [&](int a, int bb, int cc) { return e[(long)cc * sz + (long)bb * sy + a]; };
+    const IX sy = cd.nx, sz = (IX)cd.nx * cd.ny;
+    auto E = [&](int a, int bb, int cc) { return e[(IX)cc * sz + (IX)bb * sy + a]; };
     // x-direction first, then y, then z
     const T e00 = pro_lerp(E(I0, J0, K0), E(I1, J0, K0));
     const T e10 = pro_lerp(E(I0, J1, K0), E(I1, J1, K0));

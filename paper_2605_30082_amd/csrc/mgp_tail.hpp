@@ -8,9 +8,10 @@
 // steps with workgroup barriers instead of kernel boundaries.
 //
 // The iterate and the rhs of every level live in LDS for the whole V-cycle (at
-// most 2 x 4682 values), in FP32 the face coefficients too (copied in at the
-// start); otherwise only the first level's rhs and the coarsest inverse are
-// read from memory, and only the first level's result is written back.  A Gauss-Seidel half-sweep reads only cells of the
+// most 2 x 4682 values; the first level's copied in at the start), in FP32 the
+// face coefficients too; otherwise only the coarsest inverse (and in FP64 the
+// faces) are read from memory, and only the first level's result is written
+// back.  A Gauss-Seidel half-sweep reads only cells of the
 // other colour, so the sweeps run in place: the same values as the
 // out-of-place sweeps of the per-level kernels.  Every cell value comes from
 // the device functions of the per-level kernels (half_sweep_value,
@@ -32,16 +33,13 @@ constexpr int kTailMaxLevels = 16;
 constexpr int kTailFaceLds = 24576;  // FP32 face coefficients kept in LDS (96 KB)
 
 // One level as the tail kernel sees it (a table in device memory, built at
-// setup).  Only the face arrays are used; the level's b, x, t buffers are
-// those of the per-level path, which the tail keeps in LDS instead.
+// setup): its face arrays and sizes.  Its iterate and rhs live in the kernel's
+// LDS instead of the level buffers of the per-level path.
 template <typename T>
 struct TailLevel {
     const T* bx;
     const T* by;
     const T* bz;
-    T* b;
-    T* x;
-    T* t;
     Dims d;
     T h2;      // h^2 (sweeps)
     T inv_h2;  // 1 / h^2 (residual)
@@ -49,6 +47,7 @@ struct TailLevel {
 
 // One sweep of x (in LDS) in place: colour c0 (treating x as 0 if zero_in),
 // then the other colour.  fx, fy, fz: the level's faces (LDS or memory).
+// Indices in int: a level here has at most kTailCells cells.
 template <typename T>
 __device__ void tail_sweep(const T* fx, const T* fy, const T* fz, const Dims d, T h2, const T* b, T* x, int c0,
                            int zero_in)
@@ -65,13 +64,15 @@ __device__ void tail_sweep(const T* fx, const T* fy, const T* fz, const Dims d, 
 #pragma unroll
             for (int u = 0; u < kTailBatch; ++u) {
                 const int q = q0 + u * kTailNT + (int)threadIdx.x;
-                const int m = q % hx, r = q / hx;
-                const int j = r % d.ny, k = r / d.ny;
+                const int r = q / hx;
+                const int m = q - r * hx;
+                const int k = r / d.ny;
+                const int j = r - k * d.ny;
                 const int i = 2 * m + ((j + k + colour) & 1);
                 c[u] = -1;
                 if (q < cnt && i < d.nx) {
                     c[u] = (k * d.ny + j) * d.nx + i;
-                    v[u] = half_sweep_value<T>(fx, fy, fz, d, h2, b, x, zs, i, j, k);
+                    v[u] = half_sweep_value<T, int>(fx, fy, fz, d, h2, b, x, zs, i, j, k);
                 }
             }
 #pragma unroll
@@ -99,7 +100,7 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
               T* x0, T* t0, const T* __restrict__ b0, int pre, int post, int zero_init, int pre_done, int faces_lds)
 {
     __shared__ T xs[kTailLds];  // iterate of each level
-    __shared__ T bs[kTailLds];  // rhs of the levels below l0
+    __shared__ T bs[kTailLds];  // rhs of each level (the first one's copied in)
     __shared__ T fs[sizeof(T) == 4 ? kTailFaceLds : 1];  // faces of the swept levels (FP32)
     __shared__ double rs[64];
     constexpr int kTailBatch = tail_batch<T>();
@@ -121,6 +122,7 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
     };
     if (!(zero_init && pre_done == 0))
         for (int q = tid; q < ncell(0); q += kTailNT) xs[q] = x0[q];
+    for (int q = tid; q < ncell(0); q += kTailNT) bs[q] = b0[q];
     if constexpr (sizeof(T) == 4) {
         if (faces_lds) {
             for (int k = 0; k < nlv - 1; ++k) {
@@ -152,7 +154,7 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
         const T *fx, *fy, *fz;
         faces(k, fx, fy, fz);
         T* x = xs + off(k);
-        const T* b = k == 0 ? b0 : bs + off(k);
+        const T* b = bs + off(k);
         const int zi = k == 0 ? zero_init : 1;
         const int done = k == 0 ? pre_done : 0;
         if (zi && pre == 0) {
@@ -165,7 +167,7 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
         for (int q = tid; q < ncell(k + 1); q += kTailNT) {
             int I, J, K;
             cell_of(q, cd, I, J, K);
-            bc[q] = restrict_cell<T>(fx, fy, fz, L.d, L.inv_h2, b, x, I, J, K);
+            bc[q] = restrict_cell<T, int>(fx, fy, fz, L.d, L.inv_h2, b, x, I, J, K);
         }
         __syncthreads();
     }
@@ -177,14 +179,14 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
         faces(k, fx, fy, fz);
         T* x = xs + off(k);
         const T* e = xs + off(k + 1);
-        const T* b = k == 0 ? b0 : bs + off(k);
+        const T* b = bs + off(k);
         const Dims cd = lv[k + 1].d;
         for (int q0 = 0; q0 < ncell(k); q0 += kTailBatch * kTailNT) {
             T v[kTailBatch];
 #pragma unroll
             for (int u = 0; u < kTailBatch; ++u) {
                 const int q = q0 + u * kTailNT + tid;
-                if (q < ncell(k)) v[u] = x[q] + prolong_value<T>(L.d, cd, e, q);
+                if (q < ncell(k)) v[u] = x[q] + prolong_value<T, int>(L.d, cd, e, q);
             }
 #pragma unroll
             for (int u = 0; u < kTailBatch; ++u) {

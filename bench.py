@@ -69,9 +69,9 @@ TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 64, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "dc2889d950f9c4695032d5fe1b59037d56f1edb431574356b35258a695ca547e",
-    "fetch_kib": 379771.46188902244,
-    "write_kib": 149760.02689302884,
+    "sha256": "6260afe4e1f699ff6deda6d8328866370878ac911cda289c64757b89a6e22d2e",
+    "fetch_kib": 379927.83904246794,
+    "write_kib": 149760.01975661056,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

@@ -3,17 +3,18 @@
 // Below a few thousand cells a level's kernels are far shorter than a launch:
 // the pre-sweeps, residual + restriction, prolongation + correction and
 // post-sweeps of the 16^3, 8^3 ... grids would cost a dozen launches per level
-// for microseconds of work.  Here one workgroup runs all those levels and the
-// exact coarsest-grid solve (the V-cycle's recursion, Sec. 2.2), separating the
-// steps with workgroup barriers instead of kernel boundaries.
+// for microseconds of work.  Here one workgroup runs the V-cycle's recursion
+// below and including the first such level, down to the exact coarsest-grid
+// solve and back up, separating the steps with workgroup barriers instead of
+// kernel boundaries.
 //
 // The iterate and the rhs of every level live in LDS for the whole V-cycle (at
 // most 2 x 4682 values; the first level's copied in at the start), in FP32 the
 // face coefficients too; otherwise only the coarsest inverse (and in FP64 the
 // faces) are read from memory, and only the first level's result is written
-// back.  A Gauss-Seidel half-sweep reads only cells of the
-// other colour, so the sweeps run in place: the same values as the
-// out-of-place sweeps of the per-level kernels.  Every cell value comes from
+// back.  A Gauss-Seidel half-sweep reads only cells of the other colour, so
+// the sweeps run in place: the same values as the out-of-place sweeps of the
+// per-level kernels.  Every cell value comes from
 // the device functions of the per-level kernels (half_sweep_value,
 // restrict_cell, prolong_value, coarse_apply_block), so both paths give
 // identical results bit for bit.
@@ -90,7 +91,7 @@ __device__ void tail_sweep(const T* fx, const T* fy, const T* fz, const Dims d, 
 // which sweeps from one buffer into the other, leaves it).
 // faces_lds (FP32 only): the face coefficients of levels l0..nl-2 are copied
 // to LDS first (at most kTailFaceLds values together), so that no step after
-// the start reads memory except the first level's rhs and the coarsest inverse.
+// the start reads memory except the coarsest inverse.
 // Launch: one block of kTailNT threads; levels l0..nl-1 at most kTailCells
 // cells each and kTailLds together, the coarsest at most 64, nl - l0 at most
 // kTailMaxLevels.

@@ -24,7 +24,7 @@ using namespace mgp;
 
 namespace {
 
-constexpr int kMaxCoarseCells = 64;
+constexpr int kMaxCoarseCells = kCoarseMax;
 constexpr int kTimingPairs = 4096;
 constexpr int kMaxPartials = 16384;  // partial sums of one reduction (>= blocks of any launch)
 
@@ -54,7 +54,7 @@ struct mg_ctx {
     double* G = nullptr;         // coarsest inverse, n_c x n_c
     double* b0 = nullptr;        // projected rhs, finest
     double* ptmp = nullptr;      // ping-pong partner of the caller's p
-    double* work = nullptr;      // scratch (coarse inverse build; verification copies)
+    double* work = nullptr;      // scratch (verification copies)
     double* fr = nullptr;        // flexible-CG residual, direction and L direction (MG_FLAG_FCG)
     double* fd = nullptr;        // current direction: one of fd_buf
     double* fd_buf[2] = {nullptr, nullptr};
@@ -907,8 +907,7 @@ void carve(mg_ctx* c, Arena& a)
     c->ptmp = a.take<double>(n0);
     const long nc = c->lev[c->nlev - 1].n;
     c->G = a.take<double>(nc * nc);
-    const long m = nc + 1;
-    c->work = a.take<double>(std::max<long>(m * 2 * m, n0));
+    c->work = a.take<double>(n0);
     c->partials = a.take<double>(kMaxPartials);
     c->scal = a.take<double>(16);
     c->tail64 = a.take<TailLevel<double>>(MG_MAX_LEVELS);
@@ -1015,7 +1014,7 @@ int setup_impl(mg_ctx* c, const double* pbx, const double* pby, const double* pb
         }
     }
     Level& Cl = c->lev[c->nlev - 1];
-    k_coarse_inverse<<<1, kBlock, 0, c->stream>>>(Cl.f64.bx, Cl.f64.by, Cl.f64.bz, Cl.d, Cl.h, c->work, c->G,
+    k_coarse_inverse<<<1, kCoarseNT, 0, c->stream>>>(Cl.f64.bx, Cl.f64.by, Cl.f64.bz, Cl.d, Cl.h, c->G,
                                                   c->scal + 5);
     CHECK_LAUNCH(c);
     TRY(fetch_scalars(c, 6));

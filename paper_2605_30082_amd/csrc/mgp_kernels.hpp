@@ -253,24 +253,30 @@ __global__ void k_coarsen_faces(const double* __restrict__ fbx, const double* __
 // exact coarsest-grid inverse (setup, one block)
 // ---------------------------------------------------------------------------
 
+constexpr int kCoarseMax = 64;    // cells of the coarsest grid at most
+constexpr int kCoarseNT = 1024;   // threads of the coarse-inverse block
+
 // Builds the bordered matrix M = [[L, 1], [1^T, 0]] (m = n+1) of the coarsest
 // level next to an identity, reduces it by Gauss-Jordan elimination with
 // partial pivoting, and stores G = top-left n x n block of M^-1: for any r,
-// G r is the zero-mean solution of L e = r - mean(r).
-// work: m * 2m doubles; status[0] = 0 on success, 1 if singular.
-__global__ void k_coarse_inverse(const double* __restrict__ bx, const double* __restrict__ by,
-                                 const double* __restrict__ bz, Dims d, double h, double* __restrict__ work,
-                                 double* __restrict__ G, double* __restrict__ status)
+// G r is the zero-mean solution of L e = r - mean(r).  The m x 2m system lives
+// in LDS (at most 65 x 130 doubles); the pivot of a column is the first row of
+// largest magnitude, found by one wave.  status[0] = 0 on success, 1 if
+// singular.  Launch: one block of kCoarseNT threads, n <= kCoarseMax.
+__global__ void __launch_bounds__(kCoarseNT)
+k_coarse_inverse(const double* __restrict__ bx, const double* __restrict__ by, const double* __restrict__ bz, Dims d,
+                 double h, double* __restrict__ G, double* __restrict__ status)
 {
     const int n = d.nx * d.ny * d.nz, m = n + 1, w = 2 * m;
     const double h2 = h * h;
+    __shared__ double work[(kCoarseMax + 1) * 2 * (kCoarseMax + 1)];
     __shared__ int piv_row;
     __shared__ int singular;
     for (int t = threadIdx.x; t < m * w; t += blockDim.x) work[t] = 0.0;
     if (threadIdx.x == 0) singular = 0;
     __syncthreads();
     for (int c = threadIdx.x; c < m; c += blockDim.x) {
-        double* row = work + (long)c * w;
+        double* row = work + c * w;
         row[m + c] = 1.0;
         if (c == n) {
             for (int t = 0; t < n; ++t) row[t] = 1.0;
@@ -290,46 +296,70 @@ __global__ void k_coarse_inverse(const double* __restrict__ bx, const double* __
     }
     __syncthreads();
     for (int col = 0; col < m; ++col) {
-        if (threadIdx.x == 0) {
-            int p = col;
-            double best = fabs(work[(long)col * w + col]);
-            for (int r = col + 1; r < m; ++r) {
-                const double a = fabs(work[(long)r * w + col]);
-                if (a > best) { best = a; p = r; }
+        if (threadIdx.x < 64) {
+            // first row of largest |a| among rows col..m-1 (two rows per lane, then the wave)
+            const int lane = threadIdx.x;
+            double best = -1.0;
+            int p = m;
+            for (int r = col + lane; r < m; r += 64) {
+                const double a = fabs(work[r * w + col]);
+                if (r == col || a > best) {  // row col stands first, as in a serial search
+                    best = a;
+                    p = r;
+                }
             }
-            piv_row = p;
-            if (best == 0.0) singular = 1;
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_down(best, off, 64);
+                const int op = __shfl_down(p, off, 64);
+                if (ob > best || (ob == best && op < p)) {
+                    best = ob;
+                    p = op;
+                }
+            }
+            if (lane == 0) {
+                piv_row = p;
+                if (best == 0.0) singular = 1;
+            }
         }
         __syncthreads();
         if (singular) break;
         const int p = piv_row;
         if (p != col) {
             for (int t = threadIdx.x; t < w; t += blockDim.x) {
-                const double a = work[(long)col * w + t];
-                work[(long)col * w + t] = work[(long)p * w + t];
-                work[(long)p * w + t] = a;
+                const double a = work[col * w + t];
+                work[col * w + t] = work[p * w + t];
+                work[p * w + t] = a;
             }
         }
         __syncthreads();
-        const double inv = 1.0 / work[(long)col * w + col];
+        const double inv = 1.0 / work[col * w + col];
         __syncthreads();
-        for (int t = threadIdx.x; t < w; t += blockDim.x) work[(long)col * w + t] *= inv;
+        for (int t = threadIdx.x; t < w; t += blockDim.x) work[col * w + t] *= inv;
         __syncthreads();
-        // eliminate column `col` from every other row; the pivot row is read-only here
-        for (int e = threadIdx.x; e < m * w; e += blockDim.x) {
-            const int r = e / w, t = e % w;
-            if (r == col) continue;
-            const double f = work[(long)r * w + col];
-            if (t != col) work[(long)r * w + t] -= f * work[(long)col * w + t];
+        // eliminate column `col` from every other row; the pivot row is read-only
+        // here (element e = r w + t, its row and column stepped without division)
+        {
+            const int dr = (int)blockDim.x / w, dt = (int)blockDim.x % w;
+            int r = (int)threadIdx.x / w, t = (int)threadIdx.x % w;
+            for (; r < m; r += dr, t += dt) {
+                if (t >= w) {
+                    t -= w;
+                    ++r;
+                    if (r >= m) break;
+                }
+                if (r == col || t == col) continue;
+                const double f = work[r * w + col];
+                work[r * w + t] -= f * work[col * w + t];
+            }
         }
         __syncthreads();
         for (int r = threadIdx.x; r < m; r += blockDim.x)
-            if (r != col) work[(long)r * w + col] = 0.0;
+            if (r != col) work[r * w + col] = 0.0;
         __syncthreads();
     }
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int r = e / n, t = e % n;
-        G[e] = work[(long)r * w + m + t];
+        G[e] = work[r * w + m + t];
     }
     if (threadIdx.x == 0) status[0] = singular ? 1.0 : 0.0;
 }

@@ -754,35 +754,43 @@ __global__ void k_faces_from_density(const double* __restrict__ rho, Dims d, dou
     const long total = nfx + nfy + nfz;
     const long sz = (long)d.nx * d.ny;
     double bad = 0.0;
-    for (long f = (long)blockIdx.x * kBlock + threadIdx.x; f < total; f += (long)gridDim.x * kBlock) {
-        long a = -1, bcell = -1;
-        double* out;
-        long o;
-        if (f < nfx) {
-            const int i = (int)(f % rx);
-            const long row = f / rx;
-            if (i > 0 && i < d.nx) { bcell = row * d.nx + i; a = bcell - 1; }
-            out = gx; o = f;
-        } else if (f < nfx + nfy) {
-            const long t = f - nfx;
-            const int j = (int)((t / d.nx) % (d.ny + 1));
-            const int k = (int)(t / ((long)d.nx * (d.ny + 1)));
-            if (j > 0 && j < d.ny) { bcell = ((long)k * d.ny + j) * d.nx + t % d.nx; a = bcell - d.nx; }
-            out = gy; o = t;
-        } else {
-            const long t = f - nfx - nfy;
-            const int k = (int)(t / sz);
-            if (k > 0 && k < d.nz) { bcell = t; a = t - sz; }
-            out = gz; o = t;
+    // face index arithmetic in U: 32-bit unsigned where every index fits (no
+    // 64-bit divisions), else 64-bit; same faces either way
+    auto run = [&](auto zero) {
+        using U = decltype(zero);
+        const U ux = (U)d.nx, urx = (U)rx, ufx = (U)nfx, ufy = (U)nfy, usz = (U)sz, uyp = (U)d.nx * (U)(d.ny + 1);
+        for (U f = (U)blockIdx.x * kBlock + threadIdx.x; f < (U)total; f += (U)gridDim.x * kBlock) {
+            long a = -1, bcell = -1;
+            double* out;
+            U o;
+            if (f < ufx) {
+                const U row = f / urx;
+                const int i = (int)(f - row * urx);
+                if (i > 0 && i < d.nx) { bcell = (long)(row * ux) + i; a = bcell - 1; }
+                out = gx; o = f;
+            } else if (f < ufx + ufy) {
+                const U t = f - ufx;
+                const U k = t / uyp, rest = t - k * uyp;
+                const U j = rest / ux, i = rest - j * ux;
+                if (j > 0 && j < (U)d.ny) { bcell = (long)((k * (U)d.ny + j) * ux + i); a = bcell - d.nx; }
+                out = gy; o = t;
+            } else {
+                const U t = f - ufx - ufy;
+                const U k = t / usz;
+                if (k > 0 && k < (U)d.nz) { bcell = (long)t; a = (long)(t - usz); }
+                out = gz; o = t;
+            }
+            double v = 0.0;
+            if (a >= 0) {
+                const double ra = rho[a], rb = rho[bcell];
+                v = 2.0 / (ra + rb);
+                bad += (bad_coeff(v) || bad_coeff(ra) || bad_coeff(rb)) ? 1.0 : 0.0;
+            }
+            out[o] = v;
         }
-        double v = 0.0;
-        if (a >= 0) {
-            const double ra = rho[a], rb = rho[bcell];
-            v = 2.0 / (ra + rb);
-            bad += (bad_coeff(v) || bad_coeff(ra) || bad_coeff(rb)) ? 1.0 : 0.0;
-        }
-        out[o] = v;
-    }
+    };
+    if (total + (long)gridDim.x * kBlock < (1L << 32)) run(0u);
+    else run(0ul);
     if (PAD) {
         bad = block_sum(bad);
         if (threadIdx.x == 0) partials[blockIdx.x] = bad;

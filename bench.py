@@ -69,9 +69,9 @@ TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 64, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "6260afe4e1f699ff6deda6d8328866370878ac911cda289c64757b89a6e22d2e",
-    "fetch_kib": 379927.83904246794,
-    "write_kib": 149760.01975661056,
+    "sha256": "bf4a4bfe2ed61a2e607cb9ec0bb960722dbf613862fc285210f8ff2fb08672fd",
+    "fetch_kib": 380635.7838541667,
+    "write_kib": 149760.10772235578,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

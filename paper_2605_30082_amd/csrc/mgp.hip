@@ -382,9 +382,13 @@ int vcycle_tail(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init, int 
     const int pre = c->opts.pre, post = c->opts.post;
     long faces = 0;
     for (int k = l; k < c->nlev - 1; ++k) faces += n_fx(c->lev[k].d) + n_fy(c->lev[k].d) + n_fz(c->lev[k].d);
-    const int faces_lds = sizeof(T) == 4 && faces <= kTailFaceLds ? 1 : 0;
-    k_vcycle_tail<T><<<1, kTailNT, 0, c->stream>>>(tail_tab<T>(c), l, c->nlev, c->G, *x, *t, b, pre, post,
-                                                   zero_init ? 1 : 0, pre_done, faces_lds);
+    const int zi = zero_init ? 1 : 0;
+    if (sizeof(T) == 4 && faces <= kTailFaceLds)
+        k_vcycle_tail<T, sizeof(T) == 4><<<1, kTailNT, 0, c->stream>>>(tail_tab<T>(c), l, c->nlev, c->G, *x, *t, b,
+                                                                       pre, post, zi, pre_done);
+    else
+        k_vcycle_tail<T, false><<<1, kTailNT, 0, c->stream>>>(tail_tab<T>(c), l, c->nlev, c->G, *x, *t, b, pre,
+                                                              post, zi, pre_done);
     CHECK_LAUNCH(c);
     if (((pre - pre_done) + post) & 1) std::swap(*x, *t);
     return MG_OK;

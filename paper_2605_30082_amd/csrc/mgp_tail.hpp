@@ -89,20 +89,22 @@ __device__ void tail_sweep(const T* fx, const T* fy, const T* fz, const Dims d, 
 // pre_done: pre-sweeps already run on level l0.  The result goes to x0, or to
 // t0 when the sweeps on level l0 are odd in number (where the per-level path,
 // which sweeps from one buffer into the other, leaves it).
-// faces_lds (FP32 only): the face coefficients of levels l0..nl-2 are copied
-// to LDS first (at most kTailFaceLds values together), so that no step after
-// the start reads memory except the coarsest inverse.
+// FLDS (FP32 only): the face coefficients of levels l0..nl-2 are copied to LDS
+// first (at most kTailFaceLds values together), so that no step after the
+// start reads memory except the coarsest inverse; a template flag, so that
+// every face read is an LDS read by construction.
 // Launch: one block of kTailNT threads; levels l0..nl-1 at most kTailCells
 // cells each and kTailLds together, the coarsest at most 64, nl - l0 at most
 // kTailMaxLevels.
-template <typename T>
+template <typename T, bool FLDS>
 __global__ void __launch_bounds__(kTailNT)
 k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double* __restrict__ G,
-              T* x0, T* t0, const T* __restrict__ b0, int pre, int post, int zero_init, int pre_done, int faces_lds)
+              T* x0, T* t0, const T* __restrict__ b0, int pre, int post, int zero_init, int pre_done)
 {
+    static_assert(!FLDS || sizeof(T) == 4, "faces in LDS for FP32 only");
     __shared__ T xs[kTailLds];  // iterate of each level
     __shared__ T bs[kTailLds];  // rhs of each level (the first one's copied in)
-    __shared__ T fs[sizeof(T) == 4 ? kTailFaceLds : 1];  // faces of the swept levels (FP32)
+    __shared__ T fs[FLDS ? kTailFaceLds : 1];  // faces of the swept levels
     __shared__ double rs[64];
     constexpr int kTailBatch = tail_batch<T>();
     const int tid = (int)threadIdx.x;
@@ -124,8 +126,8 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
     if (!(zero_init && pre_done == 0))
         for (int q = tid; q < ncell(0); q += kTailNT) xs[q] = x0[q];
     for (int q = tid; q < ncell(0); q += kTailNT) bs[q] = b0[q];
-    if constexpr (sizeof(T) == 4) {
-        if (faces_lds) {
+    if constexpr (FLDS) {
+        {
             for (int k = 0; k < nlv - 1; ++k) {
                 T* F = fs + foff(k);
                 const int a = (int)n_fx(lv[k].d), c = (int)n_fy(lv[k].d), e = (int)n_fz(lv[k].d);
@@ -138,15 +140,14 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
     __syncthreads();
     // the faces of level k, from LDS or from memory
     auto faces = [&](int k, const T*& fx, const T*& fy, const T*& fz) {
-        fx = lv[k].bx;
-        fy = lv[k].by;
-        fz = lv[k].bz;
-        if constexpr (sizeof(T) == 4) {
-            if (faces_lds) {
-                fx = fs + foff(k);
-                fy = fx + n_fx(lv[k].d);
-                fz = fy + n_fy(lv[k].d);
-            }
+        if constexpr (FLDS) {
+            fx = fs + foff(k);
+            fy = fx + n_fx(lv[k].d);
+            fz = fy + n_fy(lv[k].d);
+        } else {
+            fx = lv[k].bx;
+            fy = lv[k].by;
+            fz = lv[k].bz;
         }
     };
 

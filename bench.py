@@ -69,9 +69,9 @@ TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 64, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "bf4a4bfe2ed61a2e607cb9ec0bb960722dbf613862fc285210f8ff2fb08672fd",
-    "fetch_kib": 380635.7838541667,
-    "write_kib": 149760.10772235578,
+    "sha256": "db88913cc568328136a28cacb3e75d71e9be89b4884d22f59b9f1369bb19516f",
+    "fetch_kib": 379905.83173076925,
+    "write_kib": 149760.01740284456,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

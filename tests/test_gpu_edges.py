@@ -263,3 +263,25 @@ def test_fused_launches_sweep_counts(pre, post, precision):
     (p0, st0), (p1, st1) = out
     assert st0.cycles == 6 and st0.hist == st1.hist
     assert torch.equal(p0, p1)
+
+
+@pytest.mark.parametrize("method", ["vcycle", "fcg"])
+def test_queued_presweeps_never_change_the_result(method):
+    """The next cycle's pre-sweeps are queued while the host waits for a norm
+    (not after the last allowed cycle, nor when the norm is expected to meet the
+    tolerance).  Stopping after cycle k by the tolerance or by max_cycles takes
+    different queueing decisions and must give the same p bit for bit."""
+    wl = W.drop_film_workload(64)
+    gb, gd = gpu_inputs(wl)
+    kw = dict(precision="mixed", zero_guess=True, method=method)
+    with S.Solver(*gb, wl.h, **kw) as s:
+        _, full = s.solve(gd, 1e-13, check=False)
+    for k in (3, 6, len(full.hist) - 2):
+        tol = full.hist[k] * (1.0 + 1e-9)
+        with S.Solver(*gb, wl.h, **kw) as s:
+            p_tol, st_tol = s.solve(gd, tol)
+        with S.Solver(*gb, wl.h, max_cycles=k, **kw) as s:
+            p_max, st_max = s.solve(gd, 1e-30, check=False)
+        assert st_tol.cycles == k and st_max.cycles == k
+        assert st_tol.hist == st_max.hist == full.hist[:k + 1]
+        assert torch.equal(p_tol, p_max)

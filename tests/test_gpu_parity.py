@@ -156,10 +156,11 @@ def test_smooth(dims, precision):
     s.close()
 
 
-# FP32 sweeps on grids at least 64 x 16 wide go in pairs through the two-sweep
-# kernel: (64, 32, 48) has a ragged last z-chunk, (96, 64, 32) a ragged last x-tile;
-# 3 sweeps = one pair + one single sweep.
-@pytest.mark.parametrize("dims", [(64, 32, 48), (96, 64, 32), (128, 64, 64)])
+# FP32 sweeps on grids at least 32 x 16 wide go in pairs through the two-sweep
+# kernel (32-wide tiles below 64 cells): (64, 32, 48) has a ragged last z-chunk,
+# (96, 64, 32) a ragged last x-tile, (32, 24, 16) a ragged last y-tile of the
+# 32-wide instance; 3 sweeps = one pair + one single sweep.
+@pytest.mark.parametrize("dims", [(64, 32, 48), (96, 64, 32), (128, 64, 64), (32, 24, 16), (32, 48, 16)])
 def test_smooth_fp32_sweep_pairs(dims):
     note(f"fp32 sweep pairs dims={dims}")
     beta = random_beta(dims, 13)

@@ -46,9 +46,75 @@ struct TailLevel {
     T inv_h2;  // 1 / h^2 (residual)
 };
 
+// The per-level kernels' stencil without its wall branches.  Wall faces are
+// stored zeros at every level, so a wall term adds +0 to the diagonal and
+// 0 * x to the off-diagonal sum: the same sums as skipping it, term by term in
+// the same order (the neighbour index is clamped into the level, where every
+// value is finite).  Indices in int: a level here has at most kTailCells cells.
+template <typename T>
+__device__ inline void tail_stencil(const T* fx, const T* fy, const T* fz, const T* x, const Dims d, int i, int j,
+                                    int k, int c, int n, T& diag, T& off)
+{
+    const int sy = d.nx, sz = d.nx * d.ny;
+    const int ix = (k * d.ny + j) * (d.nx + 2) + i, iy = (k * (d.ny + 1) + j) * d.nx + i;
+    T dg = 0, of = 0, f;
+    f = fx[ix];          dg += f; of += f * x[max(c - 1, 0)];
+    f = fx[ix + 1];      dg += f; of += f * x[min(c + 1, n - 1)];
+    f = fy[iy];          dg += f; of += f * x[max(c - sy, 0)];
+    f = fy[iy + d.nx];   dg += f; of += f * x[min(c + sy, n - 1)];
+    f = fz[c];           dg += f; of += f * x[max(c - sz, 0)];
+    f = fz[c + sz];      dg += f; of += f * x[min(c + sz, n - 1)];
+    diag = dg;
+    off = of;
+}
+
+// half_sweep_value with tail_stencil
+template <typename T>
+__device__ inline T tail_half_sweep_value(const T* fx, const T* fy, const T* fz, const Dims d, int n, T h2,
+                                          const T* b, const T* src, int zero_src, int i, int j, int k)
+{
+    const int c = (k * d.ny + j) * d.nx + i;
+    T dg, of;
+    if (zero_src) {
+        const int ix = (k * d.ny + j) * (d.nx + 2) + i, iy = (k * (d.ny + 1) + j) * d.nx + i;
+        dg = 0;
+        dg += fx[ix];
+        dg += fx[ix + 1];
+        dg += fy[iy];
+        dg += fy[iy + d.nx];
+        dg += fz[c];
+        dg += fz[c + d.nx * d.ny];
+        of = 0;
+    } else {
+        tail_stencil<T>(fx, fy, fz, src, d, i, j, k, c, n, dg, of);
+    }
+    T v;
+    if (dg > (T)0) v = (of - h2 * b[c]) / dg;
+    else v = zero_src ? (T)0 : src[c];
+    return v;
+}
+
+// restrict_cell with tail_stencil
+template <typename T>
+__device__ inline T tail_restrict_cell(const T* fx, const T* fy, const T* fz, const Dims f, T inv_h2, const T* b,
+                                       const T* x, int I, int J, int K)
+{
+    const int n = f.nx * f.ny * f.nz;
+    T s = 0;
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+                const int i = 2 * I + cx, j = 2 * J + cy, k = 2 * K + cz;
+                const int c = (k * f.ny + j) * f.nx + i;
+                T dg, of;
+                tail_stencil<T>(fx, fy, fz, x, f, i, j, k, c, n, dg, of);
+                s += b[c] - (of - dg * x[c]) * inv_h2;
+            }
+    return s * (T)0.125;
+}
+
 // One sweep of x (in LDS) in place: colour c0 (treating x as 0 if zero_in),
 // then the other colour.  fx, fy, fz: the level's faces (LDS or memory).
-// Indices in int: a level here has at most kTailCells cells.
 template <typename T>
 __device__ void tail_sweep(const T* fx, const T* fy, const T* fz, const Dims d, T h2, const T* b, T* x, int c0,
                            int zero_in)
@@ -73,7 +139,7 @@ __device__ void tail_sweep(const T* fx, const T* fy, const T* fz, const Dims d, 
                 c[u] = -1;
                 if (q < cnt && i < d.nx) {
                     c[u] = (k * d.ny + j) * d.nx + i;
-                    v[u] = half_sweep_value<T, int>(fx, fy, fz, d, h2, b, x, zs, i, j, k);
+                    v[u] = tail_half_sweep_value<T>(fx, fy, fz, d, d.nx * d.ny * d.nz, h2, b, x, zs, i, j, k);
                 }
             }
 #pragma unroll
@@ -123,6 +189,8 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
         for (int m = 0; m < k; ++m) o += nfaces(m);
         return o;
     };
+    // every iterate value a stencil may read (also at a clamped wall index) is finite
+    for (int q = tid; q < off(nlv); q += kTailNT) xs[q] = (T)0;
     if (!(zero_init && pre_done == 0))
         for (int q = tid; q < ncell(0); q += kTailNT) xs[q] = x0[q];
     for (int q = tid; q < ncell(0); q += kTailNT) bs[q] = b0[q];
@@ -169,7 +237,7 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
         for (int q = tid; q < ncell(k + 1); q += kTailNT) {
             int I, J, K;
             cell_of(q, cd, I, J, K);
-            bc[q] = restrict_cell<T, int>(fx, fy, fz, L.d, L.inv_h2, b, x, I, J, K);
+            bc[q] = tail_restrict_cell<T>(fx, fy, fz, L.d, L.inv_h2, b, x, I, J, K);
         }
         __syncthreads();
     }

@@ -14,10 +14,11 @@
 // faces) are read from memory, and only the first level's result is written
 // back.  A Gauss-Seidel half-sweep reads only cells of the other colour, so
 // the sweeps run in place: the same values as the out-of-place sweeps of the
-// per-level kernels.  Every cell value comes from
-// the device functions of the per-level kernels (half_sweep_value,
-// restrict_cell, prolong_value, coarse_apply_block), so both paths give
-// identical results bit for bit.
+// per-level kernels.  The prolongation and the coarse solve are the per-level
+// kernels' device functions (prolong_value, coarse_apply_block); the sweeps and
+// the restriction compute the same expressions in the same order, with the
+// wall terms written as +0 instead of skipped (tail_stencil), so both paths
+// give identical results bit for bit.
 #pragma once
 
 #include "mgp_kernels.hpp"

@@ -70,8 +70,8 @@ TRAFFIC = {
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
     "sha256": "db88913cc568328136a28cacb3e75d71e9be89b4884d22f59b9f1369bb19516f",
-    "fetch_kib": 379905.83173076925,
-    "write_kib": 149760.01740284456,
+    "fetch_kib": 379925.3055388622,
+    "write_kib": 149760.01978165066,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

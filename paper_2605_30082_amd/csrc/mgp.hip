@@ -121,6 +121,17 @@ int grid_for(long n)
     return (int)g;
 }
 
+// Grid-stride elementwise kernels without block partials: one element per
+// thread (up to 2^30 blocks), so that every element's loads are in flight at
+// once instead of a few per thread at a time.
+int grid_full(long n)
+{
+    long g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > (1L << 30)) g = 1L << 30;
+    return (int)g;
+}
+
 // plan: number of levels; 0 if invalid
 int plan(int nx, int ny, int nz, int coarse_max, Dims* out)
 {
@@ -397,7 +408,7 @@ int vcycle_tail(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init, int 
 template <typename T>
 int fill(mg_ctx* c, T* x, long n, T v)
 {
-    k_fill<T><<<grid_for(n), kBlock, 0, c->stream>>>(x, n, v);
+    k_fill<T><<<grid_full(n), kBlock, 0, c->stream>>>(x, n, v);
     CHECK_LAUNCH(c);
     return MG_OK;
 }
@@ -405,7 +416,7 @@ int fill(mg_ctx* c, T* x, long n, T v)
 template <typename S, typename D>
 int convert(mg_ctx* c, const S* x, long n, D* y)
 {
-    k_convert<S, D><<<grid_for(n), kBlock, 0, c->stream>>>(x, n, y);
+    k_convert<S, D><<<grid_full(n), kBlock, 0, c->stream>>>(x, n, y);
     CHECK_LAUNCH(c);
     return MG_OK;
 }
@@ -851,7 +862,7 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
     CHECK_LAUNCH(c);
     TRY(reduce_to(c, kReduceBlocks, 3));
     if (cur != p) HIP_TRY(c, hipMemcpyAsync(p, cur, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-    k_sub_scalar<<<grid_for(n), kBlock, 0, c->stream>>>(p, n, c->scal, 3, 1.0 / (double)n);
+    k_sub_scalar<<<grid_full(n), kBlock, 0, c->stream>>>(p, n, c->scal, 3, 1.0 / (double)n);
     CHECK_LAUNCH(c);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     harvest(c);
@@ -989,31 +1000,34 @@ int upload_tail(mg_ctx* c)
 int setup_impl(mg_ctx* c, const double* pbx, const double* pby, const double* pbz, const double* rho = nullptr)
 {
     Level& F = c->lev[0];
+    // up to one face per thread; one partial count of bad faces per block
+    const long faces = n_fx(F.d) + n_fy(F.d) + n_fz(F.d);
+    const int nb = (int)std::min<long>((faces + kBlock - 1) / kBlock, kMaxPartials);
     if (rho) {
         HIP_TRY(c, hipMemcpyAsync(c->rho, rho, sizeof(double) * F.n, hipMemcpyDeviceToDevice, c->stream));
-        k_faces_from_density<true><<<kReduceBlocks, kBlock, 0, c->stream>>>(c->rho, F.d, F.f64.bx, F.f64.by,
-                                                                            F.f64.bz, c->partials);
+        k_faces_from_density<true><<<nb, kBlock, 0, c->stream>>>(c->rho, F.d, F.f64.bx, F.f64.by, F.f64.bz,
+                                                                 c->partials);
     } else {
-        k_import_faces<<<kReduceBlocks, kBlock, 0, c->stream>>>(pbx, pby, pbz, F.d, F.f64.bx, F.f64.by, F.f64.bz,
-                                                                c->partials);
+        k_import_faces<<<nb, kBlock, 0, c->stream>>>(pbx, pby, pbz, F.d, F.f64.bx, F.f64.by, F.f64.bz,
+                                                     c->partials);
     }
     c->use_rho = rho != nullptr;
     CHECK_LAUNCH(c);
-    TRY(reduce_to(c, kReduceBlocks, 4));
+    TRY(reduce_to(c, nb, 4));
     for (int l = 1; l < c->nlev; ++l) {
         Level& A = c->lev[l - 1];
         Level& B = c->lev[l];
         const long nf = n_fx(B.d) + n_fy(B.d) + n_fz(B.d);
-        k_coarsen_faces<<<grid_for(nf), kBlock, 0, c->stream>>>(A.f64.bx, A.f64.by, A.f64.bz, A.d, B.d,
+        k_coarsen_faces<<<grid_full(nf), kBlock, 0, c->stream>>>(A.f64.bx, A.f64.by, A.f64.bz, A.d, B.d,
                                                                 B.f64.bx, B.f64.by, B.f64.bz);
         CHECK_LAUNCH(c);
     }
     if (c->mixed) {
         for (int l = 0; l < c->nlev; ++l) {
             Level& L = c->lev[l];
-            k_convert<double, float><<<grid_for(n_fx(L.d)), kBlock, 0, c->stream>>>(L.f64.bx, n_fx(L.d), L.f32.bx);
-            k_convert<double, float><<<grid_for(n_fy(L.d)), kBlock, 0, c->stream>>>(L.f64.by, n_fy(L.d), L.f32.by);
-            k_convert<double, float><<<grid_for(n_fz(L.d)), kBlock, 0, c->stream>>>(L.f64.bz, n_fz(L.d), L.f32.bz);
+            k_convert<double, float><<<grid_full(n_fx(L.d)), kBlock, 0, c->stream>>>(L.f64.bx, n_fx(L.d), L.f32.bx);
+            k_convert<double, float><<<grid_full(n_fy(L.d)), kBlock, 0, c->stream>>>(L.f64.by, n_fy(L.d), L.f32.by);
+            k_convert<double, float><<<grid_full(n_fz(L.d)), kBlock, 0, c->stream>>>(L.f64.bz, n_fz(L.d), L.f32.bz);
             CHECK_LAUNCH(c);
         }
     }
@@ -1263,7 +1277,7 @@ int mg_face_grad(mg_ctx* c, const double* lambda, const double* p, double* g_x, 
     Level& F = c->lev[0];
     const long total = (long)F.d.nz * F.d.ny * (F.d.nx + 1) + (long)F.d.nz * (F.d.ny + 1) * F.d.nx +
                        (long)(F.d.nz + 1) * F.d.ny * F.d.nx;
-    k_face_grad<<<grid_for(total), kBlock, 0, c->stream>>>(lambda, p, F.d, 1.0 / (F.h * F.h), g_x, g_y, g_z);
+    k_face_grad<<<grid_full(total), kBlock, 0, c->stream>>>(lambda, p, F.d, 1.0 / (F.h * F.h), g_x, g_y, g_z);
     CHECK_LAUNCH(c);
     return MG_OK;
 }
@@ -1307,7 +1321,7 @@ int mg_faces_from_vof(const double* f_drop, const double* f_film, const int dims
     const long total = (long)d.nz * d.ny * (d.nx + 1) + (long)d.nz * (d.ny + 1) * d.nx +
                        (long)(d.nz + 1) * d.ny * d.nx;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    k_faces_from_vof<<<grid_for(total), kBlock, 0, s>>>(f_drop, f_film, d, rho_drop, rho_film, rho_gas, beta_x,
+    k_faces_from_vof<<<grid_full(total), kBlock, 0, s>>>(f_drop, f_film, d, rho_drop, rho_film, rho_gas, beta_x,
                                                         beta_y, beta_z);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
@@ -1320,7 +1334,7 @@ int mg_density_from_vof(const double* f_drop, const double* f_film, const int di
     if (!(rho_drop > 0) || !(rho_film > 0) || !(rho_gas > 0)) return MG_EINVAL;
     const long n = (long)dims[0] * dims[1] * dims[2];
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    k_density_from_vof<<<grid_for(n), kBlock, 0, s>>>(f_drop, f_film, n, rho_drop, rho_film, rho_gas, rho);
+    k_density_from_vof<<<grid_full(n), kBlock, 0, s>>>(f_drop, f_film, n, rho_drop, rho_film, rho_gas, rho);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 
@@ -1333,7 +1347,7 @@ int mg_faces_from_density(const double* rho, const int dims[3], double* beta_x, 
     const long total = (long)d.nz * d.ny * (d.nx + 1) + (long)d.nz * (d.ny + 1) * d.nx +
                        (long)(d.nz + 1) * d.ny * d.nx;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    k_faces_from_density<false><<<grid_for(total), kBlock, 0, s>>>(rho, d, beta_x, beta_y, beta_z, nullptr);
+    k_faces_from_density<false><<<grid_full(total), kBlock, 0, s>>>(rho, d, beta_x, beta_y, beta_z, nullptr);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 
@@ -1345,7 +1359,7 @@ int mg_density_grad(const double* rho, const int dims[3], const double* g_x, con
     const Dims d{dims[0], dims[1], dims[2]};
     const long n = (long)d.nx * d.ny * d.nz;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    k_density_grad<<<grid_for(n), kBlock, 0, s>>>(rho, d, g_x, g_y, g_z, g_rho);
+    k_density_grad<<<grid_full(n), kBlock, 0, s>>>(rho, d, g_x, g_y, g_z, g_rho);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 
@@ -1357,7 +1371,7 @@ int mg_divergence(const double* u, const double* v, const double* w, const int d
     const Dims d{dims[0], dims[1], dims[2]};
     const long n = (long)d.nx * d.ny * d.nz;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    k_divergence<<<grid_for(n), kBlock, 0, s>>>(u, v, w, d, h, dt, b);
+    k_divergence<<<grid_full(n), kBlock, 0, s>>>(u, v, w, d, h, dt, b);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 
@@ -1371,7 +1385,7 @@ int mg_vof_grad(const double* f_drop, const double* f_film, const int dims[3], d
     const Dims d{dims[0], dims[1], dims[2]};
     const long n = (long)d.nx * d.ny * d.nz;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    k_vof_grad<<<grid_for(n), kBlock, 0, s>>>(f_drop, f_film, d, rho_drop, rho_film, rho_gas, g_x, g_y, g_z, g_drop,
+    k_vof_grad<<<grid_full(n), kBlock, 0, s>>>(f_drop, f_film, d, rho_drop, rho_film, rho_gas, g_x, g_y, g_z, g_drop,
                                              g_film);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
@@ -1384,7 +1398,7 @@ int mg_velocity_correct(const double* beta_x, const double* beta_y, const double
     const Dims d{dims[0], dims[1], dims[2]};
     const long nf = (long)d.nz * d.ny * (d.nx + 1) + (long)d.nz * (d.ny + 1) * d.nx + (long)(d.nz + 1) * d.ny * d.nx;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    k_velocity_correct<<<grid_for(nf), kBlock, 0, s>>>(beta_x, beta_y, beta_z, p, d, h, dt, u, v, w);
+    k_velocity_correct<<<grid_full(nf), kBlock, 0, s>>>(beta_x, beta_y, beta_z, p, d, h, dt, u, v, w);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 

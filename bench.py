@@ -69,9 +69,9 @@ TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 64, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "db88913cc568328136a28cacb3e75d71e9be89b4884d22f59b9f1369bb19516f",
-    "fetch_kib": 379925.3055388622,
-    "write_kib": 149760.01978165066,
+    "sha256": "35aa7411dc1cf334c4ef0f88e3f3e983de78b6aeea665df58766226076b295cf",
+    "fetch_kib": 379839.44235777244,
+    "write_kib": 149760.02196013622,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

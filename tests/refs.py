@@ -13,7 +13,10 @@ oracle's code:
 * ``layered_solve``: coefficient varying in z only and a right-hand side
   cos(pi mx x) cos(pi my y) g(z) reduce exactly to one tridiagonal system in z;
 * ``closed_form``: the discrete solution for b = -3 pi^2 cos(pi x)cos(pi y)cos(pi z)
-  at constant coefficient 1.
+  at constant coefficient 1;
+* ``MatrixMultigrid``: the multigrid cycle composed from explicit level matrices
+  (operator, restriction, prolongation), sequential point Gauss-Seidel over the
+  two colours and a dense bordered coarsest solve (tiny grids).
 """
 from __future__ import annotations
 
@@ -208,3 +211,145 @@ def closed_form(n):
 
 def rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+# ---------------------------------------------------------------------------
+# A multilevel cycle assembled from matrices (pins the oracle's V-cycle)
+# ---------------------------------------------------------------------------
+#
+# Every piece below is a matrix or a loop written from its definition; nothing
+# is taken from the oracle:
+#   * operator of level l:      A_l = -G^T B_l G / h_l^2            (dense_operator)
+#   * coarse coefficients:      coarse face = mean of the 4 fine faces that tile it
+#   * restriction R:            coarse cell = mean of its 8 children (matrix of 1/8)
+#   * prolongation P:           tensor product of the 1-D cell-centred linear
+#                               interpolation (3/4 parent, 1/4 the parent's
+#                               neighbour on the fine cell's side; at a wall the
+#                               parent stands in for the missing neighbour)
+#   * smoother:                 sequential point Gauss-Seidel with unit relaxation
+#                               over the cells of one colour, (i+j+k) mod 2
+#   * coarsest grid:            dense bordered solve [[A, 1], [1^T, 0]]
+# and the cycle composes them: `pre` sweeps of (red, black), residual, restrict,
+# recurse from zero, prolongate and add, `post` sweeps of (black, red).
+
+def coarse_faces_from_definition(beta):
+    """Coarse face coefficients: each coarse face is the arithmetic mean of the
+    four fine faces lying in it; wall faces are zero."""
+    bx, by, bz = beta
+    nz, ny, nx1 = bx.shape
+    nx = nx1 - 1
+    cx, cy, cz = nx // 2, ny // 2, nz // 2
+    fx = bx[:, :, 0:nx + 1:2]                         # fine x-faces on coarse x-face planes
+    cbx = fx.reshape(cz, 2, cy, 2, cx + 1).mean(axis=(1, 3))
+    fy = by[:, 0:ny + 1:2, :]
+    cby = fy.reshape(cz, 2, cy + 1, cx, 2).mean(axis=(1, 4))
+    fz = bz[0:nz + 1:2, :, :]
+    cbz = fz.reshape(cz + 1, cy, 2, cx, 2).mean(axis=(2, 4))
+    cbx[:, :, 0] = cbx[:, :, cx] = 0.0
+    cby[:, 0, :] = cby[:, cy, :] = 0.0
+    cbz[0] = cbz[cz] = 0.0
+    return cbx, cby, cbz
+
+
+def restriction_matrix(dims):
+    """R (coarse cells x fine cells): 1/8 at each of a coarse cell's 8 children."""
+    nx, ny, nz = dims
+    R = np.zeros((nx * ny * nz // 8, nx * ny * nz))
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                parent = ((k // 2) * (ny // 2) + j // 2) * (nx // 2) + i // 2
+                R[parent, (k * ny + j) * nx + i] = 0.125
+    return R
+
+
+def linear_interp_1d(nf):
+    """1-D cell-centred interpolation (nf x nf/2): fine cell i lies in parent
+    I = i // 2, a quarter cell towards neighbour I - 1 (i even) or I + 1 (i odd)."""
+    nc = nf // 2
+    P = np.zeros((nf, nc))
+    for i in range(nf):
+        parent = i // 2
+        nb = parent - 1 if i % 2 == 0 else parent + 1
+        if nb < 0 or nb >= nc:
+            nb = parent                     # wall: the parent replaces the missing neighbour
+        P[i, parent] += 0.75
+        P[i, nb] += 0.25
+    return P
+
+
+def prolongation_matrix(dims):
+    """P (fine cells x coarse cells) = Pz (x) Py (x) Px for x-fastest ordering."""
+    nx, ny, nz = dims
+    return np.kron(linear_interp_1d(nz), np.kron(linear_interp_1d(ny), linear_interp_1d(nx)))
+
+
+def colour_of_cells(dims):
+    nx, ny, nz = dims
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return ((i + j + k) % 2).ravel()
+
+
+def gauss_seidel_colour(A, b, x, colour_mask):
+    """Sequential point Gauss-Seidel over the cells of one colour, in index
+    order: x_i = (b_i - sum_{j != i} A_ij x_j) / A_ii, each update seen by the next."""
+    for i in np.flatnonzero(colour_mask):
+        row = A[i]
+        x[i] = (b[i] - (row @ x - row[i] * x[i])) / row[i]
+    return x
+
+
+def bordered_solve(A, r):
+    n = A.shape[0]
+    M = np.zeros((n + 1, n + 1))
+    M[:n, :n] = A
+    M[:n, n] = 1.0
+    M[n, :n] = 1.0
+    return np.linalg.solve(M, np.concatenate([r, [0.0]]))[:n]
+
+
+class MatrixMultigrid:
+    """Level matrices for the cycle above; `coarse_max` as in the solver: halve
+    every dimension while any exceeds it."""
+
+    def __init__(self, beta, h, coarse_max=4):
+        self.A, self.R, self.P, self.colour = [], [], [], []
+        bx = beta[0]
+        nz, ny, nx1 = bx.shape
+        dims = (nx1 - 1, ny, nz)
+        while True:
+            self.A.append(dense_operator(beta, h))
+            self.colour.append(colour_of_cells(dims))
+            if max(dims) <= coarse_max:
+                break
+            self.R.append(restriction_matrix(dims))
+            self.P.append(prolongation_matrix(dims))
+            beta = coarse_faces_from_definition(beta)
+            dims = tuple(d // 2 for d in dims)
+            h = 2.0 * h
+
+    def cycle(self, level, b, x, pre, post, post_order=(1, 0)):
+        A = self.A[level]
+        if level == len(self.A) - 1:
+            return bordered_solve(A, b)
+        red = self.colour[level] == 0
+        black = ~red
+        for _ in range(pre):
+            gauss_seidel_colour(A, b, x, red)
+            gauss_seidel_colour(A, b, x, black)
+        r = b - A @ x
+        e = self.cycle(level + 1, self.R[level] @ r, np.zeros(self.R[level].shape[0]), pre, post, post_order)
+        x += self.P[level] @ e
+        masks = {0: red, 1: black}
+        for _ in range(post):
+            gauss_seidel_colour(A, b, x, masks[post_order[0]])
+            gauss_seidel_colour(A, b, x, masks[post_order[1]])
+        return x
+
+    def cycles(self, rhs, x0, count, pre=2, post=2, post_order=(1, 0)):
+        """`count` cycles on L x = rhs - mean(rhs) from x0 (mean of x kept)."""
+        b = rhs.ravel() - rhs.mean()
+        x = np.array(x0, dtype=np.float64).ravel().copy()
+        for _ in range(count):
+            x = self.cycle(0, b, x, pre, post, post_order)
+        return x.reshape(rhs.shape)

@@ -646,3 +646,79 @@ def test_density_gradient_matches_finite_differences(oracle_mod):
         rm[idx] -= eps
         fdiff = (J(rp) - J(rm)) / (2 * eps)
         assert abs(fdiff - got[idx]) <= 1e-6 * abs(got[idx]) + 1e-9 * np.abs(got).max(), (idx, fdiff, got[idx])
+
+
+# ---------------------------------------------------------------------------
+# the V-cycle composition (readings R8-R13 of the multigrid the paper names in
+# Sec. 4.3.2): the oracle's cycles against a cycle assembled from matrices
+# ---------------------------------------------------------------------------
+
+def random_density_faces(dims, seed):
+    """Harmonic-mean faces of a log-uniform density in [1.2, 1000] (numpy only)."""
+    nx, ny, nz = dims
+    rho = np.exp(rng(seed).uniform(np.log(1.2), np.log(1000.0), (nz, ny, nx)))
+    bx = np.zeros((nz, ny, nx + 1))
+    by = np.zeros((nz, ny + 1, nx))
+    bz = np.zeros((nz + 1, ny, nx))
+    bx[:, :, 1:nx] = 2.0 / (rho[:, :, :-1] + rho[:, :, 1:])
+    by[:, 1:ny, :] = 2.0 / (rho[:, :-1, :] + rho[:, 1:, :])
+    bz[1:nz, :, :] = 2.0 / (rho[:-1, :, :] + rho[1:, :, :])
+    return bx, by, bz
+
+
+def test_matrix_multigrid_pieces_follow_their_definitions():
+    """The matrix reference's own pieces: R and P map constants to constants,
+    P reproduces linear functions at interior fine cells, and the coarse faces
+    of constant faces are constant with zero walls."""
+    dims = (8, 4, 6)
+    R = refs.restriction_matrix(dims)
+    P = refs.prolongation_matrix(dims)
+    np.testing.assert_allclose(R @ np.ones(R.shape[1]), 1.0, rtol=0, atol=0)
+    np.testing.assert_allclose(P @ np.ones(P.shape[1]), 1.0, rtol=0, atol=1e-15)
+    # a linear function of the coarse x centre is reproduced at interior fine centres
+    nx, ny, nz = dims
+    xc = (np.arange(nx // 2) + 0.5) * 2.0
+    coarse = np.broadcast_to(xc[None, None, :], (nz // 2, ny // 2, nx // 2)).ravel()
+    fine = (P @ coarse).reshape(nz, ny, nx)
+    xf = np.arange(nx) + 0.5
+    np.testing.assert_allclose(fine[:, :, 1:-1], np.broadcast_to(xf[1:-1], (nz, ny, nx - 2)), atol=1e-14)
+    cb = refs.coarse_faces_from_definition(refs.constant_beta(dims, 0.5))
+    for a, ref in zip(cb, refs.constant_beta((4, 2, 3), 0.5)):
+        np.testing.assert_array_equal(a, ref)
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8), (16, 16, 16), (16, 8, 8)])
+@pytest.mark.parametrize("pre,post", [(2, 2), (1, 3)])
+def test_vcycles_match_matrix_multigrid(oracle_mod, dims, pre, post):
+    """One and three oracle V-cycles (from a random guess, on a random density
+    with a 1000/1.2 contrast) equal the matrix-assembled cycle to rounding."""
+    nx, ny, nz = dims
+    h = 1.0 / nx
+    beta = random_density_faces(dims, seed=11)
+    g = rng(12)
+    rhs = g.standard_normal((nz, ny, nx))
+    p0 = g.standard_normal((nz, ny, nx))
+    mg = refs.MatrixMultigrid(beta, h)
+    assert len(mg.A) == oracle_mod.num_levels(dims)
+    for count in (1, 3):
+        ref = mg.cycles(rhs, p0, count, pre, post)
+        got = oracle_mod.vcycles(beta, rhs, h, count, p0=p0, pre=pre, post=post)
+        assert refs.rel_l2(got, ref) <= 1e-12, (dims, pre, post, count)
+
+
+def test_vcycle_pin_detects_a_changed_composition(oracle_mod):
+    """The comparison above can tell compositions apart: swapping the
+    post-smoothing colour order, or moving a sweep from post to pre, changes
+    one cycle by far more than rounding."""
+    dims = (8, 8, 8)
+    h = 1.0 / 8
+    beta = random_density_faces(dims, seed=11)
+    g = rng(12)
+    rhs = g.standard_normal((8, 8, 8))
+    p0 = g.standard_normal((8, 8, 8))
+    mg = refs.MatrixMultigrid(beta, h)
+    got = oracle_mod.vcycles(beta, rhs, h, 1, p0=p0, pre=2, post=2)
+    swapped = mg.cycles(rhs, p0, 1, 2, 2, post_order=(0, 1))
+    shifted = mg.cycles(rhs, p0, 1, 3, 1)
+    assert refs.rel_l2(got, swapped) > 1e-6
+    assert refs.rel_l2(got, shifted) > 1e-6

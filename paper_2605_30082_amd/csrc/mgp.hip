@@ -42,6 +42,12 @@ struct Level {
     LevelBufs<float> f32;
 };
 
+// what one timed launch recorded (MG_FLAG_TIMING)
+struct EvSlot {
+    int cls, level;
+    double bytes;
+};
+
 }  // namespace
 
 struct mg_ctx {
@@ -76,10 +82,8 @@ struct mg_ctx {
     bool valid = false;          // coefficients imported and accepted
     // timing
     hipEvent_t sync_ev = nullptr;  // marks the scalar copy the mixed loop waits for
-    hipEvent_t* ev = nullptr;
-    int ev_class[kTimingPairs];
-    int ev_level[kTimingPairs];
-    double ev_bytes[kTimingPairs];
+    hipEvent_t* ev = nullptr;      // 2 * kTimingPairs events and their records (MG_FLAG_TIMING)
+    EvSlot* ev_slot = nullptr;
     int ev_used = 0;
     unsigned timing_mask = (1u << MG_K_COUNT) - 1;  // classes timed under MG_FLAG_TIMING
     double kms[MG_K_COUNT], kms0[MG_K_COUNT];
@@ -122,15 +126,23 @@ int grid_for(long n)
 }
 
 // Grid-stride elementwise kernels without block partials: one element per
-// thread (up to 2^30 blocks), so that every element's loads are in flight at
-// once instead of a few per thread at a time.
-int grid_full(long n)
+// thread, so that every element's loads are in flight at once instead of a few
+// per thread at a time.  A dispatch holds at most 2^32 - 1 work-items per
+// dimension, so the grid is capped there and the grid-stride loop covers the
+// rest (face counts of the largest grids plan() accepts exceed 2^32).
+constexpr long kMaxGridBlocks = 0xFFFFFFFFL / kBlock;
+
+constexpr int grid_full(long n)
 {
     long g = (n + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
-    if (g > (1L << 30)) g = 1L << 30;
+    if (g > kMaxGridBlocks) g = kMaxGridBlocks;
     return (int)g;
 }
+// 1536 x 1024 x 1024 cells (< 2^31, accepted by plan()) have 4.8e9 faces
+static_assert((long)grid_full(3L * 1536 * 1024 * 1024 + 4096L * 1024) * kBlock <= 0xFFFFFFFFL,
+              "face-sized grids stay within the dispatch limit");
+static_assert(grid_full(1000) == 4 && grid_full(0) == 1, "one element per thread below the cap");
 
 // plan: number of levels; 0 if invalid
 int plan(int nx, int ny, int nz, int coarse_max, Dims* out)
@@ -173,9 +185,7 @@ struct TimedLaunch {
         if (!c->ev || !tiled || !((c->timing_mask >> k) & 1u) || c->ev_used >= kTimingPairs) return;
         on = true;
         slot = c->ev_used;
-        c->ev_class[slot] = k;
-        c->ev_level[slot] = level;
-        c->ev_bytes[slot] = bytes;
+        c->ev_slot[slot] = EvSlot{k, level, bytes};
     }
     hipEvent_t start() const { return on ? c->ev[2 * slot] : nullptr; }
     hipEvent_t stop() const { return on ? c->ev[2 * slot + 1] : nullptr; }
@@ -193,14 +203,14 @@ void harvest(mg_ctx* c, int ready = -1)
     for (int t = 0; t < ready; ++t) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->ev[2 * t], c->ev[2 * t + 1]) == hipSuccess) {
-            const int k = c->ev_class[t];
-            c->kms[k] += ms;
-            c->klaunch[k] += 1;
-            c->kbytes[k] += c->ev_bytes[t];
-            if (c->ev_level[t] == 0) {
-                c->kms0[k] += ms;
-                c->klaunch0[k] += 1;
-                c->kbytes0[k] += c->ev_bytes[t];
+            const EvSlot& r = c->ev_slot[t];
+            c->kms[r.cls] += ms;
+            c->klaunch[r.cls] += 1;
+            c->kbytes[r.cls] += r.bytes;
+            if (r.level == 0) {
+                c->kms0[r.cls] += ms;
+                c->klaunch0[r.cls] += 1;
+                c->kbytes0[r.cls] += r.bytes;
             }
         }
     }
@@ -208,9 +218,7 @@ void harvest(mg_ctx* c, int ready = -1)
         const int u = t - ready;
         std::swap(c->ev[2 * u], c->ev[2 * t]);
         std::swap(c->ev[2 * u + 1], c->ev[2 * t + 1]);
-        c->ev_class[u] = c->ev_class[t];
-        c->ev_level[u] = c->ev_level[t];
-        c->ev_bytes[u] = c->ev_bytes[t];
+        c->ev_slot[u] = c->ev_slot[t];
     }
     c->ev_used -= ready;
 }
@@ -894,6 +902,7 @@ void free_ctx(mg_ctx* c)
             if (c->ev[t]) (void)hipEventDestroy(c->ev[t]);
         delete[] c->ev;
     }
+    delete[] c->ev_slot;
     if (c->sync_ev) (void)hipEventDestroy(c->sync_ev);
     if (c->arena) (void)hipFree(c->arena);
     if (c->host_scal) (void)hipHostFree(c->host_scal);
@@ -1170,7 +1179,8 @@ int setup_ctx(mg_ctx** out, const double* beta_x, const double* beta_y, const do
     }
     if (o.flags & MG_FLAG_TIMING) {
         c->ev = new (std::nothrow) hipEvent_t[2 * kTimingPairs]();
-        if (!c->ev) return fail(MG_ENOMEM);
+        c->ev_slot = new (std::nothrow) EvSlot[kTimingPairs];
+        if (!c->ev || !c->ev_slot) return fail(MG_ENOMEM);
         // timing-only events: no system-scope fence (cache write-back and
         // invalidate) at each record, which would stall the next kernel; they are
         // read only after the stream has been synchronised
@@ -1270,6 +1280,10 @@ int mg_solve_adjoint(mg_ctx* c, const double* g, double* lambda, double tol, mg_
 int mg_face_grad(mg_ctx* c, const double* lambda, const double* p, double* g_x, double* g_y, double* g_z)
 {
     TRY(check_ctx(c));
+    if (!c->valid) {
+        set_err(c, "the context holds rejected face coefficients: call mg_update first");
+        return MG_EINVAL;
+    }
     if (!lambda || !p || !g_x || !g_y || !g_z) {
         set_err(c, "NULL argument");
         return MG_EINVAL;

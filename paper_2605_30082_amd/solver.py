@@ -124,6 +124,10 @@ class Solver:
             self._ctx = ctypes.c_void_p(None)
             raise MgError(st, L.last_error(None))
         self.device = (rho if rho is not None else beta_x).device
+        # bumped by every coefficient import (update / update_density), so that a
+        # caller holding a version can tell whether the hierarchy still holds the
+        # coefficients it imported
+        self.coef_version = 0
 
     @classmethod
     def from_density(cls, rho: torch.Tensor, h: float, **kw) -> "Solver":
@@ -137,6 +141,10 @@ class Solver:
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             self._lib.mg_destroy(self._ctx)
             self._ctx = ctypes.c_void_p(None)
+
+    @property
+    def closed(self) -> bool:
+        return getattr(self, "_ctx", None) is None or not self._ctx.value
 
     def __del__(self):
         try:
@@ -175,12 +183,14 @@ class Solver:
     def update(self, beta_x: torch.Tensor, beta_y: torch.Tensor, beta_z: torch.Tensor) -> None:
         """New face coefficients for the same grid (no allocation)."""
         shapes = face_shapes(self.dims)
+        self.coef_version += 1
         self._check(self._lib.mg_update(self._ctx, _ptr(beta_x, "beta_x", shapes[0]),
                                         _ptr(beta_y, "beta_y", shapes[1]), _ptr(beta_z, "beta_z", shapes[2])))
         self.density = False
 
     def update_density(self, rho: torch.Tensor) -> None:
         """New cell density (contexts made from a density only; no allocation)."""
+        self.coef_version += 1
         self._check(self._lib.mg_update_density(self._ctx, _ptr(rho, "rho", self.cell_shape)))
         self.density = True
 

@@ -234,3 +234,66 @@ def test_gradient_reaches_density():
         b[idx] -= eps
         fdiff = (loss(a) - loss(b)) / (2 * eps)
         assert abs(fdiff - got[idx]) <= 1e-4 * abs(got[idx]) + 1e-6 * gmax, (idx, fdiff, got[idx])
+
+
+def test_persistent_solver_reused_without_setup(monkeypatch):
+    """poisson_solve(solver=s): two forwards on different coefficients, backwards
+    in the opposite order, all on one hierarchy (no new Solver is built; the
+    backward re-imports its own coefficients when a later forward replaced them).
+    Results equal those of a hierarchy built per call, bit for bit."""
+    import paper_2605_30082_amd.autograd as A
+    wl = W.drop_film_workload(16)
+    w = T(W.loss_weights(wl.dims))
+    gb, gd = gpu_inputs(wl)
+    gb2 = tuple(a * 1.5 for a in gb)                 # a second set of coefficients
+
+    def run(beta, solver):
+        rhs = leaf(gd)
+        bs = [leaf(a) for a in beta]
+        p = poisson_solve(rhs, *bs, wl.h, tol=1e-12, solver=solver)
+        return p, rhs, bs
+
+    ref = []
+    for beta in (gb, gb2):
+        p, rhs, bs = run(beta, None)
+        (w * p).sum().backward()
+        ref.append((p.detach(), rhs.grad, [b.grad for b in bs]))
+    s = S.Solver(*gb, wl.h, zero_guess=True)
+    built = []
+
+    class Counting(S.Solver):
+        def __init__(self, *a, **k):
+            built.append(1)
+            super().__init__(*a, **k)
+
+    monkeypatch.setattr(A, "Solver", Counting)
+    got = [run(beta, s) for beta in (gb, gb2)]
+    for k in (1, 0):                                 # backward of the second forward first
+        p, rhs, bs = got[k]
+        (w * p).sum().backward()
+    assert not built
+    for (p, rhs, bs), (rp, rg, rb) in zip(got, ref):
+        assert torch.equal(p.detach(), rp) and torch.equal(rhs.grad, rg)
+        for b, r in zip(bs, rb):
+            assert torch.equal(b.grad, r)
+    s.close()
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_backward_twice(persistent):
+    """A retained graph can be differentiated again: the second backward gives the
+    same gradients as the first (nothing the first one freed is needed)."""
+    wl = W.drop_film_workload(16)
+    w = T(W.loss_weights(wl.dims))
+    gb, gd = gpu_inputs(wl)
+    rhs = leaf(gd)
+    bs = [leaf(a) for a in gb]
+    s = S.Solver(*gb, wl.h, zero_guess=True) if persistent else None
+    p = poisson_solve(rhs, *bs, wl.h, tol=1e-12, solver=s)
+    loss = (w * p).sum()
+    g1 = torch.autograd.grad(loss, [rhs, *bs], retain_graph=True)
+    g2 = torch.autograd.grad(loss, [rhs, *bs])
+    for a, b in zip(g1, g2):
+        assert torch.equal(a, b)
+    if s is not None:
+        s.close()

@@ -9,8 +9,16 @@ supplies sampled values of its own solutions stopped at relative residuals of
 make_oracle_samples.py).
 The exact z-layered solution (tridiagonal reduction, the real 960/1.2 density
 jump) is checked at 512^3 as a property that holds at any size.
+
+Whole-field parity at 512^3: the oracle solves the film + 32 drops workload
+inline (FP64 V-cycles, stopped at rr 1e-10 by the same rule as the GPU, then
+continued to rr 1e-13), and every GPU solve of the benchmark's configuration is
+compared with it over all 134M cells.  The differentiable configuration (the
+drop-film field at 256^3, loss sum(w p), adjoint to 1e-10) is compared with
+the oracle's gradients over every cell and face.
 """
 import os
+import time
 
 import numpy as np
 import pytest
@@ -36,6 +44,21 @@ def big():
     ob, od = oracle_inputs(wl)
     del wl.u, wl.v, wl.w
     return wl, gb, gd, ob, od
+
+
+@pytest.fixture(scope="module")
+def big_oracle(big):
+    """The oracle's solutions of the 512^3 workload: stopped by the GPU's rule at
+    rr 1e-10, and continued from there to rr 1e-13 (the converged solution)."""
+    wl, gb, gd, ob, od = big
+    t0 = time.time()
+    r10 = oracle.solve(ob, od, wl.h, tol=1e-10)
+    note(f"oracle 512^3 to rr 1e-10: {r10.cycles} cycles, rr {r10.rel_res:.3e}, {time.time() - t0:.1f} s")
+    t0 = time.time()
+    r13 = oracle.solve(ob, od, wl.h, tol=1e-13, p0=r10.p)
+    note(f"oracle 512^3 continued to rr 1e-13: {r13.cycles} more cycles, rr {r13.rel_res:.3e}, "
+         f"{time.time() - t0:.1f} s")
+    return r10, r13
 
 
 def true_rr(ob, od, p, h):
@@ -270,3 +293,70 @@ def test_largest_arrays_layered_exact():
             assert torch.equal(pd, p)
             del pd, rho_t
         del p
+
+
+@pytest.mark.parametrize("precision,method", [("mixed", "vcycle"), ("fp64", "vcycle"),
+                                              ("mixed", "fcg"), ("fp64", "fcg")])
+def test_whole_field_512_vs_oracle(big, big_oracle, precision, method):
+    """The benchmark's configuration (hierarchy from the cell density, p = 0,
+    rr 1e-10) against the oracle over all 134M cells: relative L2 <= 1e-9 from
+    the converged solution; the V-cycle solves also against the oracle stopped
+    by the same rule after the same number of cycles (FP64: rounding order
+    only)."""
+    wl, gb, gd, ob, od = big
+    r10, r13 = big_oracle
+    rho = S.density_from_vof(T(wl.f_drop), T(wl.f_film), wl.rho_drop, wl.rho_film, wl.rho_gas)
+    with S.Solver.from_density(rho, wl.h, precision=precision, zero_guess=True, method=method) as s:
+        p, st = s.solve(gd, 1e-10)
+    del rho
+    pg = N(p)
+    del p
+    err = rel_l2(pg, r13.p)
+    note(f"512^3 {precision} {method}: {st.cycles} iterations, rr {st.rel_res:.3e}, "
+         f"whole-field rel L2 vs converged oracle {err:.3e}")
+    assert st.rel_res <= 1e-10
+    assert err <= 1e-9
+    if method == "vcycle":
+        same = rel_l2(pg, r10.p)
+        note(f"  vs the oracle stopped by the same rule ({r10.cycles} cycles): whole-field rel L2 {same:.3e}")
+        assert st.cycles == r10.cycles
+        assert same <= (1e-11 if precision == "fp64" else 1e-9)
+
+
+@pytest.mark.parametrize("precision,persistent", [("fp64", False), ("mixed", True)])
+def test_differentiable_drop_film_256(precision, persistent):
+    """Loss = sum(w p), w ~ N(0, 1) (seed 2), on the drop-film field at 256^3: the
+    forward and the adjoint solve to rr 1e-10 through the autograd function (a
+    hierarchy per call, or one persistent Solver re-used by forward and backward),
+    against the oracle's p, lambda = dLoss/drhs and dLoss/dbeta over every cell and
+    interior face, and the adjoint's own residual recomputed by the oracle."""
+    from paper_2605_30082_amd.autograd import poisson_solve
+    wl = W.drop_film_workload(256)
+    w = W.loss_weights(wl.dims)
+    gb, gd = gpu_inputs(wl)
+    ob, od = oracle_inputs(wl)
+    rhs = gd.clone().requires_grad_(True)
+    bx, by, bz = (a.clone().requires_grad_(True) for a in gb)
+    solver = S.Solver(*gb, wl.h, precision=precision, zero_guess=True) if persistent else None
+    t0 = time.time()
+    p = poisson_solve(rhs, bx, by, bz, wl.h, tol=1e-10, precision=precision, solver=solver)
+    (T(w) * p).sum().backward()
+    torch.cuda.synchronize()
+    note(f"drop film 256^3 {precision} autograd (persistent solver: {persistent}): "
+         f"forward + backward {time.time() - t0:.2f} s")
+    if solver is not None:
+        solver.close()
+    t0 = time.time()
+    p_o, lam_o, g_o = oracle.gradients(ob, od, w, wl.h, tol=1e-13)
+    note(f"  oracle gradients {time.time() - t0:.1f} s")
+    lam = N(rhs.grad)
+    wz = w - w.mean()
+    adj_rr = float(np.linalg.norm(oracle.residual(ob, wz, lam, wl.h)) / np.linalg.norm(wz))
+    e_p, e_lam = rel_l2(N(p), p_o), rel_l2(lam, lam_o)
+    e_g = [rel_l2(N(a), r) for a, r in zip((bx.grad, by.grad, bz.grad), g_o)]
+    note(f"  rel L2: p {e_p:.3e}, lambda {e_lam:.3e}, g_beta {max(e_g):.3e}; adjoint rr {adj_rr:.3e}")
+    assert adj_rr <= 1.000001e-10
+    assert e_p <= 1e-9 and e_lam <= 1e-9
+    assert max(e_g) <= 1e-8
+    gx, gy, gz = (N(a) for a in (bx.grad, by.grad, bz.grad))
+    assert not gx[:, :, [0, -1]].any() and not gy[:, [0, -1], :].any() and not gz[[0, -1]].any()

@@ -244,6 +244,33 @@ void mg_destroy(mg_ctx *c);
  * mg_last_error(NULL) gives the reason the calling thread's last mg_setup failed. */
 const char *mg_last_error(const mg_ctx *c);
 
+/*
+ * mg_solve_noalloc -- mg_setup followed by mg_solve, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): no device, pinned or host-heap allocation, no event, no
+ * allocating library routine.  The level hierarchy, copies and reduction
+ * buffers live in one static device buffer of MG_NOALLOC_SCRATCH_BYTES per GPU
+ * (held from the first call on that GPU until the process ends); the context
+ * lives on the caller's stack for the duration of the call.
+ *   beta_x/y/z, dims, h, bc, opts   as for mg_setup (MG_FLAG_TIMING: MG_EINVAL).
+ *   rhs, p, tol, st                 as for mg_solve.
+ *   hip_stream                      as for mg_setup.
+ * A grid whose hierarchy (with these options) does not fit the buffer gets
+ * MG_EINVAL and a text stating the bytes it needs (e.g. 64^3 fits in every
+ * mode, 128^3 does not).  Results equal those of mg_setup + mg_solve on the same
+ * arguments bit for bit; the mixed-precision loop cannot overlap its next
+ * pre-smoothing with the host's wait for a norm, so it may run a little slower.
+ * The buffer keeps the last call's contents; every value a call reads is
+ * written by that call first.  Calls that overlap on one GPU (from two host
+ * threads, or on two streams) race on the buffer: serialise them.  Returns
+ * after the stream has finished the call's work.  mg_last_error(NULL) gives
+ * the reason of the calling thread's last failure.
+ */
+#define MG_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int mg_solve_noalloc(const double *beta_x, const double *beta_y, const double *beta_z, const int dims[3],
+                     double h, int bc, const mg_opts *opts, const double *rhs, double *p, double tol,
+                     mg_stats *st, void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Inputs of the solve, from the flow state (no context)
  * ------------------------------------------------------------------------- */

@@ -18,6 +18,7 @@ MG_PREC_FP64, MG_PREC_MIXED = 0, 1
 MG_FLAG_ZERO_GUESS, MG_FLAG_TIMING, MG_FLAG_FCG, MG_FLAG_LEVEL_LAUNCHES = 1, 2, 4, 8
 MG_HIST_MAX = 256
 MG_MAX_LEVELS = 16
+MG_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 MG_K_SWEEP, MG_K_RESTRICT, MG_K_PROLONG, MG_K_OUTER, MG_K_NORM, MG_K_SWEEP2, MG_K_COUNT = 0, 1, 2, 3, 4, 5, 6
 
 STATUS_NAMES = {
@@ -76,6 +77,8 @@ SIGNATURES = {
     "mg_prolong_correct": (_I, [_CTX, _I, _I, _D, _D]),
     "mg_coarse_solve": (_I, [_CTX, _D, _D]),
     "mg_residual_norm2": (_I, [_CTX, _D, _D, ctypes.POINTER(ctypes.c_double)]),
+    "mg_solve_noalloc": (_I, [_D, _D, _D, _DIMS, _F, _I, ctypes.POINTER(MgOpts), _D, _D, _F,
+                              ctypes.POINTER(MgStats), ctypes.c_void_p]),
 }
 
 _lib = None

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "mgp_kernels.hpp"
@@ -69,7 +70,9 @@ struct mg_ctx {
     double* rho = nullptr;       // cell density (contexts made by mg_setup_density)
     bool use_rho = false;        // finest FP64 passes form coefficients from rho
     double* scal = nullptr;      // device scalars
-    double* host_scal = nullptr; // pinned host mirror
+    double* host_scal = nullptr; // host mirror: pinned (mg_setup) or host_scal_buf (mg_solve_noalloc)
+    double host_scal_buf[16];
+    bool caller_memory = false;  // context and arena are not the library's to free (mg_solve_noalloc)
     // levels tail_lev..nlev-1 run as one single-workgroup launch (-1: none)
     int tail_lev = -1;
     TailLevel<double>* tail64 = nullptr;  // device tables (arena)
@@ -81,7 +84,7 @@ struct mg_ctx {
     double setup_ms = 0.0;
     bool valid = false;          // coefficients imported and accepted
     // timing
-    hipEvent_t sync_ev = nullptr;  // marks the scalar copy the mixed loop waits for
+    hipEvent_t sync_ev = nullptr;  // marks the scalar copy the mixed loop waits for (NULL: wait for the stream)
     hipEvent_t* ev = nullptr;      // 2 * kTimingPairs events and their records (MG_FLAG_TIMING)
     EvSlot* ev_slot = nullptr;
     int ev_used = 0;
@@ -237,14 +240,17 @@ int reduce_to(mg_ctx* c, int nparts, int slot)
 int fetch_scalars_begin(mg_ctx* c, int count, int* ready)
 {
     HIP_TRY(c, hipMemcpyAsync(c->host_scal, c->scal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipEventRecord(c->sync_ev, c->stream));
+    if (c->sync_ev) HIP_TRY(c, hipEventRecord(c->sync_ev, c->stream));
     *ready = c->ev_used;
     return MG_OK;
 }
 
+// Without an event (mg_solve_noalloc) the wait covers the work queued after the
+// copy as well: same results, no overlap of that work with the host's wait.
 int fetch_scalars_end(mg_ctx* c, int ready)
 {
-    HIP_TRY(c, hipEventSynchronize(c->sync_ev));
+    if (c->sync_ev) HIP_TRY(c, hipEventSynchronize(c->sync_ev));
+    else HIP_TRY(c, hipStreamSynchronize(c->stream));
     harvest(c, ready);
     return MG_OK;
 }
@@ -896,7 +902,7 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
 
 void free_ctx(mg_ctx* c)
 {
-    if (!c) return;
+    if (!c || c->caller_memory) return;
     if (c->ev) {
         for (int t = 0; t < 2 * kTimingPairs; ++t)
             if (c->ev[t]) (void)hipEventDestroy(c->ev[t]);
@@ -1095,15 +1101,26 @@ int mg_plan_levels(const int dims[3], int coarse_max)
 
 namespace {
 
-// mg_setup (rho == NULL) and mg_setup_density (faces NULL)
+// Memory a context is built in when the library may not allocate
+// (mg_solve_noalloc): the host context and a device arena of `cap` bytes.
+struct CallerMemory {
+    mg_ctx* host;
+    void* arena;
+    size_t cap;
+};
+
+// mg_setup (rho == NULL) and mg_setup_density (faces NULL); with mem, in that
+// memory, without any allocation
 int setup_ctx(mg_ctx** out, const double* beta_x, const double* beta_y, const double* beta_z, const double* rho,
-              const int dims[3], double h, int bc, const mg_opts* opts, void* hip_stream)
+              const int dims[3], double h, int bc, const mg_opts* opts, void* hip_stream,
+              const CallerMemory* mem = nullptr)
 {
     if (!out) return MG_EINVAL;
     *out = nullptr;
     const double t0 = now_ms();
-    mg_ctx* c = new (std::nothrow) mg_ctx();
+    mg_ctx* c = mem ? new (mem->host) mg_ctx() : new (std::nothrow) mg_ctx();
     if (!c) return MG_ENOMEM;
+    c->caller_memory = mem != nullptr;
     c->err[0] = 0;
     c->opts = opts ? *opts : mg_opts{2, 2, 100, 4, MG_PREC_FP64, 0};
     const mg_opts& o = c->opts;
@@ -1131,6 +1148,10 @@ int setup_ctx(mg_ctx** out, const double* beta_x, const double* beta_y, const do
         (o.precision != MG_PREC_FP64 && o.precision != MG_PREC_MIXED) ||
         (o.flags & ~(MG_FLAG_ZERO_GUESS | MG_FLAG_TIMING | MG_FLAG_FCG | MG_FLAG_LEVEL_LAUNCHES))) {
         set_err(c, "invalid options");
+        return fail(MG_EINVAL);
+    }
+    if (mem && (o.flags & MG_FLAG_TIMING)) {
+        set_err(c, "MG_FLAG_TIMING creates events: not available without allocation");
         return fail(MG_EINVAL);
     }
     Dims ds[MG_MAX_LEVELS];
@@ -1161,21 +1182,34 @@ int setup_ctx(mg_ctx** out, const double* beta_x, const double* beta_y, const do
     Arena sizing{nullptr, 0, 0};
     carve(c, sizing);
     c->arena_bytes = sizing.off;
-    if (hipMalloc(&c->arena, c->arena_bytes) != hipSuccess) {
+    if (mem) {
+        if (c->arena_bytes > mem->cap) {
+            set_err(c, "a %d x %d x %d grid needs %zu bytes of device scratch with these options; the "
+                       "no-allocation buffer holds %zu",
+                    dims[0], dims[1], dims[2], c->arena_bytes, mem->cap);
+            return fail(MG_EINVAL);
+        }
+        c->arena = mem->arena;
+    } else if (hipMalloc(&c->arena, c->arena_bytes) != hipSuccess) {
         set_err(c, "hipMalloc of %zu bytes failed", c->arena_bytes);
         (void)hipGetLastError();
         return fail(MG_ENOMEM);
     }
     Arena a{static_cast<char*>(c->arena), 0, c->arena_bytes};
     carve(c, a);
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->host_scal), sizeof(double) * 16, hipHostMallocDefault) !=
-        hipSuccess) {
-        set_err(c, "pinned host allocation failed");
-        return fail(MG_ENOMEM);
-    }
-    if (hipEventCreateWithFlags(&c->sync_ev, hipEventDisableTiming) != hipSuccess) {
-        set_err(c, "hipEventCreate failed");
-        return fail(MG_EHIP);
+    if (mem) {
+        // pageable mirror and no event: the scalar reads wait for the stream
+        c->host_scal = c->host_scal_buf;
+    } else {
+        if (hipHostMalloc(reinterpret_cast<void**>(&c->host_scal), sizeof(double) * 16, hipHostMallocDefault) !=
+            hipSuccess) {
+            set_err(c, "pinned host allocation failed");
+            return fail(MG_ENOMEM);
+        }
+        if (hipEventCreateWithFlags(&c->sync_ev, hipEventDisableTiming) != hipSuccess) {
+            set_err(c, "hipEventCreate failed");
+            return fail(MG_EHIP);
+        }
     }
     if (o.flags & MG_FLAG_TIMING) {
         c->ev = new (std::nothrow) hipEvent_t[2 * kTimingPairs]();
@@ -1533,6 +1567,77 @@ int mg_residual_norm2(mg_ctx* c, const double* b, const double* p, double* norm2
     harvest(c);
     *norm2 = c->host_scal[6];
     return MG_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Solve without allocation (mg_solve_noalloc)
+// ===========================================================================
+
+// Device scratch of mg_solve_noalloc: the level hierarchy, copies and reduction
+// buffers of one set-up-and-solve.  Each GPU the library runs on holds its own
+// copy until the process ends, and every call on that GPU reuses it.  In host
+// code `scratch` is only a stand-in for the symbol: its device address comes
+// from hipGetSymbolAddress (scratch_address), never from the name.
+static __device__ __align__(256) double scratch[MG_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices];  // device address of `scratch` on each device, once looked up
+
+// Address of `scratch` on the current device (looked up on the first call there).
+int scratch_address(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices) {
+        std::snprintf(g_setup_err, sizeof(g_setup_err), "device %d beyond the %d devices mg_solve_noalloc serves",
+                      dev, kMaxScratchDevices);
+        return MG_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            std::snprintf(g_setup_err, sizeof(g_setup_err), "hipGetSymbolAddress(scratch) failed on device %d: %s",
+                          dev, hipGetErrorString(e));
+            return MG_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_solve_noalloc(const double* beta_x, const double* beta_y, const double* beta_z, const int dims[3], double h,
+                     int bc, const mg_opts* opts, const double* rhs, double* p, double tol, mg_stats* st,
+                     void* hip_stream)
+{
+    g_setup_err[0] = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        std::snprintf(g_setup_err, sizeof(g_setup_err), "no HIP device");
+        return MG_EHIP;
+    }
+    void* ptr = nullptr;
+    TRY(scratch_address(dev, &ptr));
+    // the context lives on this call's stack and its arena in `scratch`
+    mg_ctx local;
+    const CallerMemory mem{&local, ptr, MG_NOALLOC_SCRATCH_BYTES};
+    mg_ctx* c = nullptr;
+    TRY(setup_ctx(&c, beta_x, beta_y, beta_z, nullptr, dims, h, bc, opts, hip_stream, &mem));
+    const int status = solve_impl(c, rhs, p, tol, st);
+    if (status != MG_OK) {
+        std::snprintf(g_setup_err, sizeof(g_setup_err), "%s", c->err);
+        (void)hipStreamSynchronize(c->stream);  // nothing of this call still runs in `scratch`
+    }
+    return status;
 }
 
 }  // extern "C"

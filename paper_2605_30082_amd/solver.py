@@ -288,6 +288,35 @@ class Solver:
         return out.value
 
 
+def solve_noalloc(beta_x: torch.Tensor, beta_y: torch.Tensor, beta_z: torch.Tensor, h: float,
+                  rhs: torch.Tensor, p: torch.Tensor, tol: float = 1e-10, precision: str = "fp64",
+                  pre: int = 2, post: int = 2, max_cycles: int = 100, coarse_max: int = 4,
+                  zero_guess: bool = False, method: str = "vcycle", level_launches: bool = False,
+                  stream: Optional[torch.cuda.Stream] = None, check: bool = True) -> SolveStats:
+    """Set up and solve in one call that allocates nothing (mg_solve_noalloc): the
+    hierarchy lives in the library's static per-GPU scratch buffer, so grids are
+    limited to what fits in MG_NOALLOC_SCRATCH_BYTES.  p (the initial guess unless
+    zero_guess) is overwritten with the solution; same results as Solver(...).solve."""
+    nz, ny, nx1 = beta_x.shape
+    dims = (nx1 - 1, ny, nz)
+    shapes = face_shapes(dims)
+    cells = (nz, ny, nx1 - 1)
+    prec = {"fp64": L.MG_PREC_FP64, "mixed": L.MG_PREC_MIXED}.get(precision)
+    if prec is None or method not in ("vcycle", "fcg"):
+        raise MgError(L.MG_EINVAL, f"bad precision {precision!r} or method {method!r}")
+    flags = ((L.MG_FLAG_ZERO_GUESS if zero_guess else 0) | (L.MG_FLAG_FCG if method == "fcg" else 0)
+             | (L.MG_FLAG_LEVEL_LAUNCHES if level_launches else 0))
+    opts = L.MgOpts(pre, post, max_cycles, coarse_max, prec, flags)
+    st = L.MgStats()
+    status = L.load().mg_solve_noalloc(_ptr(beta_x, "beta_x", shapes[0]), _ptr(beta_y, "beta_y", shapes[1]),
+                                       _ptr(beta_z, "beta_z", shapes[2]), L.dims_arg(dims), float(h),
+                                       L.MG_BC_NEUMANN, ctypes.byref(opts), _ptr(rhs, "rhs", cells),
+                                       _ptr(p, "p", cells), float(tol), ctypes.byref(st), _stream_handle(stream))
+    if check and status != L.MG_OK:
+        raise MgError(status, L.last_error(None))
+    return SolveStats.from_c(st)
+
+
 # ---------------------------------------------------------------------------
 # inputs of the solve
 # ---------------------------------------------------------------------------

@@ -36,13 +36,15 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-1e-10 residual & smoother HBM GB/s at 512³, FP64 vs FP32+refinement"
 HBM_PEAK_GBPS = 8000.0
-KERNEL_NAMES = ["sweep", "residual_restrict", "prolong_correct", "outer_update", "residual_norm", "sweep2"]
-SWEEPS_PER_LAUNCH = {"sweep": 1, "sweep2": 2}
+KERNEL_NAMES = ["sweep", "residual_restrict", "prolong_correct", "outer_update", "residual_norm", "sweep2",
+                "sweep2_restrict"]
+SWEEPS_PER_LAUNCH = {"sweep": 1, "sweep2": 2, "sweep2_restrict": 2}
 # kernel symbol timed for each class (one per class and precision), as rocprofv3 names it
 KERNEL_SYMBOLS = {
     ("sweep", "mixed"): "mgp::k_sweep_fused<float, 8, false>",
     ("sweep", "fp64"): "mgp::k_sweep_fused<double, 16, false>",
     ("sweep2", "mixed"): "mgp::k_sweep2_fused<float, 64, 16>",
+    ("sweep2_restrict", "mixed"): "mgp::k_sweep2_restrict<16>",
     ("residual_restrict", "mixed"): "mgp::k_resid<float, 1, false>",
     ("residual_restrict", "fp64"): "mgp::k_resid<double, 1, {rho}>",
     ("prolong_correct", "mixed"): "mgp::k_prolong_tiled<float>",
@@ -109,12 +111,17 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solves")
     ap.add_argument("--no-fcg", action="store_true", help="skip the flexible-CG variant solves")
+    ap.add_argument("--no-single-thread", action="store_true",
+                    help="skip the oracle's one-thread V-cycle of the CPU baseline")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: all available)")
     ap.add_argument("--coefficients", choices=["density", "faces"], default="density",
                     help="hand the solver the cell density (coefficients formed on the fly in the finest "
                          "FP64 residual passes) or the three face arrays")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (scales PMC byte counters)")
+    ap.add_argument("--probe-smoothers", action="store_true",
+                    help="only run the finest-grid smoother kernels alone through mg_smooth (3 launches each: "
+                         "FP32 two-sweep, FP64 one-sweep) on the workload, for per-launch profiler counters")
     return ap.parse_args()
 
 
@@ -239,6 +246,54 @@ def copy_calibration() -> int:
     return 0
 
 
+def probe_smoothers(args) -> int:
+    """The finest-grid smoothers alone, through the single-kernel entry points
+    mg_smooth and mg_presmooth_restrict, on the workload's density field: three
+    FP32 two-sweep launches (k_sweep2_fused<float, 64, 16>, from a non-zero
+    iterate), three FP32 pre-smoothing launches from zero that also restrict the
+    residual (k_sweep2_restrict<16>) and three FP64 one-sweep launches
+    (k_sweep_fused<double, 16, false>).  The entry points also cast their FP64
+    arguments to the context's FP32 copies and back (k_convert launches).
+    Prints one JSON line of HIP-event times around each call."""
+    import numpy as np
+    import torch
+
+    from paper_2605_30082_amd import solver as S
+    from paper_2605_30082_amd import workloads as W
+
+    S.L.load()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    kw = {"count": args.drops} if args.workload == "many_drops" else {}
+    wl = W.make(args.workload, args.n, **kw)
+
+    def T(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    rho = S.density_from_vof(T(wl.f_drop), T(wl.f_film), wl.rho_drop, wl.rho_film, wl.rho_gas)
+    b = S.divergence(T(wl.u), T(wl.v), T(wl.w), wl.h, wl.dt)
+    b -= b.mean()
+    out = {"probe": "smoothers", "n": wl.dims[0]}
+    for name, prec in (("sweep2", "mixed"), ("sweep2_restrict", "mixed"), ("sweep64", "fp64")):
+        with S.Solver.from_density(rho, wl.h, precision=prec) as s:
+            p = b.clone()
+            times = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                if name == "sweep2_restrict":
+                    p, _ = s.presmooth_restrict(b, level=0, precision=prec)
+                else:
+                    p = s.smooth(b, p, level=0, sweeps=2 if name == "sweep2" else 1, precision=prec)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            out[name] = {"call_ms": times}
+        log(f"probe {name}: {times}")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -248,6 +303,8 @@ def main() -> int:
         return 2
     if args.copy_calibration:
         return copy_calibration()
+    if args.probe_smoothers:
+        return probe_smoothers(args)
 
     import numpy as np
     import torch
@@ -439,7 +496,13 @@ def main() -> int:
                     "alg_bytes_per_launch": d["alg_bytes_per_launch"],
                     "finest": d["finest"]}
         tr = roofline["traffic"]
+        # achieved/frac count the algorithmic bytes of the work a launch does (a two-sweep
+        # launch: two sweeps at the per-sweep unit, plus the prolongation pass it replaces);
+        # traffic_gbps/traffic_frac are what the HBM counters saw move in that time
+        roofline["achieved_is"] = ("algorithmic bytes of the work done per launch / launch time (effective "
+                                   "bandwidth; one pass over memory does two sweeps)")
         roofline["traffic_gbps"] = tr / (d["avg_ms"] * 1e-3) / 1e9 if tr else None
+        roofline["traffic_frac"] = roofline["traffic_gbps"] / HBM_PEAK_GBPS if tr else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -482,9 +545,57 @@ def main() -> int:
     return 0
 
 
-def cpu_baseline(wl, args, cycles, sample_cycles=12):
-    """The FP64 oracle on the host cores: a few V-cycles at full size (about 10 s of
-    CPU work), scaled to the cycle count of the GPU solve."""
+def host_cpu():
+    """CPU model, physical cores and logical CPUs this process may run on (Linux /proc)."""
+    model, cores = None, set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None and core is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None and core is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": model, "physical_cores": len(cores) or None, "logical_cpus_usable": usable}
+
+
+def _rss_kib(field):
+    with open("/proc/self/status") as f:
+        for line in f:
+            if line.startswith(field + ":"):
+                return int(line.split()[1])
+    return None
+
+
+def reset_peak_rss() -> bool:
+    """Reset this process's peak resident set (VmHWM) to its current size."""
+    try:
+        with open("/proc/self/clear_refs", "w") as f:
+            f.write("5")
+        return True
+    except OSError:
+        return False
+
+
+def cpu_baseline(wl, args, gpu_cycles):
+    """The FP64 oracle on the host: the whole V-cycle solve to the same tolerance
+    from p = 0 (its level hierarchy built inside, as the solve does it), on all
+    threads; then one V-cycle on one thread.  Peak resident memory over the solve."""
     import numpy as np
 
     import oracle
@@ -493,27 +604,36 @@ def cpu_baseline(wl, args, cycles, sample_cycles=12):
     threads = oracle.get_threads()
     beta = oracle.faces_from_vof(wl.f_drop, wl.f_film, wl.rho_drop, wl.rho_film, wl.rho_gas)
     b = oracle.divergence(wl.u, wl.v, wl.w, wl.h, wl.dt)
+    rss0 = _rss_kib("VmRSS")
+    peak_reset = reset_peak_rss()
     t0 = time.perf_counter()
-    lvl = beta
-    while min(lvl[0].shape[0], lvl[0].shape[1], lvl[0].shape[2] - 1) > 4:
-        lvl = oracle.coarsen_faces(lvl)
-    t_hier = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    p = oracle.vcycles(beta, b, wl.h, sample_cycles)
-    t_cycles_build = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    r = oracle.residual(beta, b - b.mean(), p, wl.h)
-    _ = float(np.linalg.norm(r))
-    t_res = time.perf_counter() - t0
-    t_cycle = max(t_cycles_build - t_hier, 0.0) / sample_cycles
-    est_ms = (t_hier + t_res + cycles * (t_cycle + t_res)) * 1e3
-    log(f"oracle: hierarchy {t_hier:.1f} s, cycle {t_cycle:.2f} s (mean of {sample_cycles}), "
-        f"residual {t_res:.1f} s, threads {threads}")
-    return {"value": est_ms, "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": f"{sample_cycles} FP64 V-cycles + a residual of the oracle on the same {wl.dims[0]}^3 "
-                      f"input (plus its coarse-level build), scaled to the GPU FP64 cycle count {cycles}",
-            "measured_s": {"hierarchy": t_hier, "cycle": t_cycle, "residual": t_res,
-                           "sample_total": t_hier + t_cycles_build + t_res}}
+    res = oracle.solve(beta, b, wl.h, tol=args.tol)
+    t_solve = time.perf_counter() - t0
+    peak = _rss_kib("VmHWM")
+    log(f"oracle: solve {t_solve:.1f} s, {res.cycles} cycles, rr {res.rel_res:.2e}, threads {threads}")
+    one = None
+    if not args.no_single_thread:
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.vcycles(beta, b, wl.h, 1)
+        one = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        log(f"oracle: one V-cycle on 1 thread {one:.1f} s")
+    del beta, b
+    return {"value": t_solve * 1e3, "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"the oracle's whole FP64 V-cycle solve of the same {wl.dims[0]}^3 input from p = 0 to rr "
+                      f"{args.tol:g} ({res.cycles} cycles; the GPU FP64 solve took {gpu_cycles}), on {threads} "
+                      f"threads, hierarchy build included",
+            "cycles": res.cycles, "rel_res": res.rel_res,
+            "single_thread_one_cycle_s": one,
+            "single_thread_note": "one V-cycle on one thread, including the oracle's level-hierarchy build and "
+                                  "the first touch of its arrays",
+            "host": host_cpu(),
+            "peak_rss_gib": (peak / 2 ** 20) if (peak is not None and peak_reset) else None,
+            "rss_before_gib": rss0 / 2 ** 20 if rss0 is not None else None,
+            "oracle_added_rss_gib": ((peak - rss0) / 2 ** 20) if (peak is not None and peak_reset and rss0) else None,
+            "rss_note": "VmHWM of the bench process over the oracle solve (peak reset at its start); the process "
+                        "also holds the workload's host arrays and the GPU runtime"}
 
 
 if __name__ == "__main__":

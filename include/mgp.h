@@ -83,12 +83,16 @@ enum {
     MG_FLAG_LEVEL_LAUNCHES = 8  /* run every step of a V-cycle as its own launch.  By default
                                 (1) the levels of at most 4096 cells that no tiled kernel
                                 serves (16^3 and below; every level of grids that small) run
-                                in one single-workgroup launch, and (2) in MG_PREC_MIXED the
+                                in one single-workgroup launch, (2) in MG_PREC_MIXED the
                                 first two-sweep launch of a post-smoothing adds the
                                 prolongated coarse correction itself (no separate
-                                prolongation pass).  Both compute every value as the
-                                separate launches do: identical results, fewer launches and
-                                HBM passes.  For comparison and testing. */
+                                prolongation pass), and (3) in MG_PREC_MIXED with pre = 2,
+                                the pre-smoothing launch of a level also forms the
+                                residual of its result and restricts it to the next level
+                                (no separate residual + restriction pass).  All three
+                                compute every value as the separate launches do: identical
+                                results, fewer launches and HBM passes.  For comparison and
+                                testing. */
 };
 
 /*
@@ -118,7 +122,9 @@ enum {
     MG_K_OUTER = 3,      /* FP64 update + residual + cast (mixed) */
     MG_K_NORM = 4,       /* residual norm */
     MG_K_SWEEP2 = 5,     /* two red-black sweeps per launch (FP32 smoothing pairs) */
-    MG_K_COUNT = 6
+    MG_K_SWEEP2R = 6,    /* FP32 pre-smoothing pair from a zero iterate that also writes the
+                            restricted residual (one launch for both; see MG_FLAG_LEVEL_LAUNCHES) */
+    MG_K_COUNT = 7
 };
 
 typedef struct {
@@ -206,7 +212,17 @@ int mg_update(mg_ctx *c, const double *beta_x, const double *beta_y, const doubl
 int mg_set_timing_classes(mg_ctx *c, unsigned mask);
 
 /*
- * mg_solve -- p = zero-mean solution of L p = rhs - mean(rhs).
+ * mg_solve -- p = zero-mean solution of L p = rhs - mean(rhs): the pressure
+ * projection that makes the corrected velocity meet the continuity equation
+ * (Sec. 2, eqs. "ns_mass" and "mom_mass"), by multigrid V-cycles (the solver
+ * whose "switch levels" Sec. 4.3.2 names; the paper gives no further detail,
+ * so the cycle is this library's reading: red-black Gauss-Seidel, pre sweeps
+ * red then black, post sweeps black then red, restriction by the mean of the
+ * 8 children, trilinear prolongation, coarse faces as the mean of the 4 fine
+ * faces they cover, the coarsest grid solved exactly).  The rhs is projected
+ * to zero mean because L annihilates constants; the stopping test is checked
+ * after every cycle (MG_PREC_MIXED: after every FP64 defect-correction step
+ * around one FP32 V-cycle).
  *   rhs   device [nz][ny][nx]; not modified.
  *   p     device [nz][ny][nx], 16-byte aligned; in: initial guess (unless
  *         MG_FLAG_ZERO_GUESS), out: solution.
@@ -220,7 +236,8 @@ int mg_solve(mg_ctx *c, const double *rhs, double *p, double tol, mg_stats *st);
 
 /*
  * mg_solve_adjoint -- lambda = zero-mean solution of L lambda = g - mean(g).
- * L is symmetric, so the adjoint of the solve is the same solve; g is dLoss/dp.
+ * L is symmetric, so the adjoint of the solve of mg_solve (Sec. 2) is the same
+ * solve; g is dLoss/dp and lambda = dLoss/drhs.
  * Same arguments, flags and return codes as mg_solve.
  */
 int mg_solve_adjoint(mg_ctx *c, const double *g, double *lambda, double tol, mg_stats *st);
@@ -228,13 +245,19 @@ int mg_solve_adjoint(mg_ctx *c, const double *g, double *lambda, double tol, mg_
 /*
  * mg_face_grad -- derivative of a loss through the solve with respect to each
  * face coefficient: g_f = (lambda_R - lambda_L)(p_R - p_L) / h^2 on interior
- * faces, 0 on walls.  lambda from mg_solve_adjoint, p from mg_solve (device,
- * cell layout); g_x/g_y/g_z device, face layouts.  One fused pass.
+ * faces, 0 on walls (the chain rule through the operator of mg_solve, whose
+ * face coefficient is the 1/rho of Sec. 2: with Loss = sum w p and
+ * L lambda = w, dLoss/dbeta_f = +(delta lambda)(delta p)/h^2 across the face).
+ * lambda from mg_solve_adjoint, p from mg_solve (device, cell layout);
+ * g_x/g_y/g_z device, face layouts.  One fused pass.  MG_EINVAL on NULL
+ * arguments or a context holding rejected coefficients.
  */
 int mg_face_grad(mg_ctx *c, const double *lambda, const double *p,
                  double *g_x, double *g_y, double *g_z);
 
-/* mg_apply -- y = L x on the finest grid (device cell arrays; must not alias). */
+/* mg_apply -- y = L x on the finest grid, L the cell-centred finite-volume
+ * operator defined at the top of this file (the discretisation of Sec. 2's
+ * variable-density pressure equation); device cell arrays that must not alias. */
 int mg_apply(mg_ctx *c, const double *x, double *y);
 
 /* mg_destroy -- free the context (NULL is ignored). */
@@ -387,6 +410,16 @@ int mg_smooth(mg_ctx *c, int level, int precision, const double *b, double *p,
 /* b_coarse = restriction (mean of 8 children) of (b - L p) on level -> level+1 */
 int mg_residual_restrict(mg_ctx *c, int level, int precision, const double *b, const double *p,
                          double *b_coarse);
+
+/* The pre-smoothing of a V-cycle on `level` followed by the restriction of its
+ * residual (the steps of the cycle before the coarse-grid correction): p
+ * (written) = the opts.pre sweeps of order 0 from p = 0; b_coarse (written,
+ * level+1 layout) = mean of the 8 children of b - L p.  In FP32 with pre = 2
+ * this is the single launch a V-cycle uses on grids at least 64 x 16 cells in
+ * (x, y) with even extents (unless MG_FLAG_LEVEL_LAUNCHES); the results equal
+ * those of mg_smooth from p = 0 followed by mg_residual_restrict bit for bit. */
+int mg_presmooth_restrict(mg_ctx *c, int level, int precision, const double *b, double *p,
+                          double *b_coarse);
 
 /* p += trilinear prolongation of e_coarse (level+1 -> level) */
 int mg_prolong_correct(mg_ctx *c, int level, int precision, const double *e_coarse, double *p);

@@ -19,7 +19,7 @@ MG_FLAG_ZERO_GUESS, MG_FLAG_TIMING, MG_FLAG_FCG, MG_FLAG_LEVEL_LAUNCHES = 1, 2, 
 MG_HIST_MAX = 256
 MG_MAX_LEVELS = 16
 MG_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
-MG_K_SWEEP, MG_K_RESTRICT, MG_K_PROLONG, MG_K_OUTER, MG_K_NORM, MG_K_SWEEP2, MG_K_COUNT = 0, 1, 2, 3, 4, 5, 6
+MG_K_SWEEP, MG_K_RESTRICT, MG_K_PROLONG, MG_K_OUTER, MG_K_NORM, MG_K_SWEEP2, MG_K_SWEEP2R, MG_K_COUNT = range(8)
 
 STATUS_NAMES = {
     MG_OK: "MG_OK", MG_EINVAL: "MG_EINVAL", MG_ENOMEM: "MG_ENOMEM", MG_EHIP: "MG_EHIP",
@@ -74,6 +74,7 @@ SIGNATURES = {
     "mg_level_faces": (_I, [_CTX, _I, _D, _D, _D]),
     "mg_smooth": (_I, [_CTX, _I, _I, _D, _D, _I, _I]),
     "mg_residual_restrict": (_I, [_CTX, _I, _I, _D, _D, _D]),
+    "mg_presmooth_restrict": (_I, [_CTX, _I, _I, _D, _D, _D]),
     "mg_prolong_correct": (_I, [_CTX, _I, _I, _D, _D]),
     "mg_coarse_solve": (_I, [_CTX, _D, _D]),
     "mg_residual_norm2": (_I, [_CTX, _D, _D, ctypes.POINTER(ctypes.c_double)]),

@@ -14,8 +14,10 @@
 #include <new>
 
 #include "mgp_kernels.hpp"
+#include "mgp_faces.hpp"
 #include "mgp_sweep.hpp"
 #include "mgp_sweep2.hpp"
+#include "mgp_sweep2r.hpp"
 #include "mgp_krylov.hpp"
 #include "mgp_resid.hpp"
 #include "mgp_tail.hpp"
@@ -309,6 +311,34 @@ int sweep_pair(mg_ctx* c, int l, const float* b, const float* in, float* out, in
     return MG_OK;
 }
 
+// The pre-smoothing pair of level l from a zero iterate (order 0, into out)
+// that also writes the restriction of its residual into bc (the rhs of level
+// l + 1): the separate residual + restriction pass is not needed.
+int sweep_pair_restrict(mg_ctx* c, int l, const float* b, float* out, float* bc)
+{
+    Level& L = c->lev[l];
+    LevelBufs<float>& B = L.f32;
+    // algorithmic bytes of the work done: two sweeps, plus the residual + restriction pass it replaces
+    const double bytes = 2.0 * (double)L.n * sweep_bytes_per_cell<float>() +
+                         (double)L.n * (5.0 + 1.0 / 8.0) * sizeof(float);
+    TimedLaunch tl(c, l, MG_K_SWEEP2R, bytes, true);
+    const hipError_t e = launch_sweep2_restrict(B.bx, B.by, B.bz, L.d, (float)(L.h * L.h),
+                                                (float)(1.0 / (L.h * L.h)), b, out, bc, 0, c->stream, tl.start(),
+                                                tl.stop());
+    if (e != hipSuccess) {
+        set_err(c, "sweep launch failed: %s", hipGetErrorString(e));
+        return MG_EHIP;
+    }
+    return MG_OK;
+}
+
+// whether the pre-smoothing of level l runs as one launch with the restriction
+bool fused_restrict(const mg_ctx* c, int l)
+{
+    return c->opts.pre == 2 && l < c->nlev - 1 && !(c->tail_lev >= 0 && l >= c->tail_lev) &&
+           !(c->opts.flags & MG_FLAG_LEVEL_LAUNCHES) && sweep2r_ok(c->lev[l].d);
+}
+
 // `count` sweeps of one order on level l from *x (zero_in: from 0) with *t as
 // the ping-pong partner; on return *x holds the result.  FP32 pairs of sweeps
 // run in the two-sweep kernel where the grid allows it.
@@ -331,6 +361,25 @@ int smooth(mg_ctx* c, int l, const T* b, T** x, T** t, int order, int count, boo
         std::swap(*x, *t);
     }
     return MG_OK;
+}
+
+// All pre-sweeps of level l from a zero iterate; on return *x holds the result.
+// *restricted: the same launch also wrote the restricted residual into the rhs
+// of level l + 1 (FP32 levels that fused_restrict accepts).
+template <typename T>
+int presmooth(mg_ctx* c, int l, const T* b, T** x, T** t, bool* restricted)
+{
+    *restricted = false;
+    if constexpr (sizeof(T) == 4) {
+        if (fused_restrict(c, l)) {
+            const int e = sweep_pair_restrict(c, l, b, *t, bufs<float>(c->lev[l + 1]).b);
+            if (e != MG_OK) return e;
+            std::swap(*x, *t);
+            *restricted = true;
+            return MG_OK;
+        }
+    }
+    return smooth<T>(c, l, b, x, t, 0, c->opts.pre, true);
 }
 
 template <typename T>
@@ -443,19 +492,22 @@ int convert(mg_ctx* c, const S* x, long n, D* y)
 
 // One V-cycle on level l.  *x holds the iterate (zero_init: treat as 0),
 // *t is its ping-pong partner; on return *x holds the result (the two
-// pointers may have been swapped).  pre_done pre-sweeps have already run.
+// pointers may have been swapped).  pre_done pre-sweeps have already run
+// (by presmooth, when pre_done = pre and zero_init; restricted: that launch
+// also wrote the rhs of level l + 1).
 template <typename T>
-int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init, int pre_done = 0)
+int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init, int pre_done = 0, bool restricted = false)
 {
     Level& L = c->lev[l];
     if (l == c->nlev - 1) return coarse_apply<T>(c, b, *x);
     if (c->tail_lev >= 0 && l >= c->tail_lev) return vcycle_tail<T>(c, l, x, t, b, zero_init, pre_done);
     const int pre = c->opts.pre, post = c->opts.post;
     if (zero_init && pre == 0) TRY(fill<T>(c, *x, L.n, (T)0));
-    TRY(smooth<T>(c, l, b, x, t, 0, pre - pre_done, zero_init && pre_done == 0));
+    if (zero_init && pre_done == 0 && pre > 0) TRY(presmooth<T>(c, l, b, x, t, &restricted));
+    else TRY(smooth<T>(c, l, b, x, t, 0, pre - pre_done, zero_init && pre_done == 0));
     Level& C = c->lev[l + 1];
     LevelBufs<T>& CB = bufs<T>(C);
-    TRY(residual_restrict<T>(c, l, b, *x, CB.b));
+    if (!restricted) TRY(residual_restrict<T>(c, l, b, *x, CB.b));
     T* cx = CB.x;
     T* ct = CB.t;
     TRY(vcycle<T>(c, l + 1, &cx, &ct, CB.b, true));
@@ -633,7 +685,7 @@ int fcg_loop(mg_ctx* c, double* x, double bnorm, double tol, bool zero_guess, mg
     // as in the mixed V-cycle loop: the next preconditioner's pre-sweeps are
     // queued while the host waits for the norm, unless it is expected to converge
     const int pre = c->opts.pre;
-    bool queued = false;
+    bool queued = false, queued_restricted = false;
     double rr_before = -1.0;
     float* zx32 = F.f32.x;
     float* zt32 = F.f32.t;
@@ -646,7 +698,7 @@ int fcg_loop(mg_ctx* c, double* x, double bnorm, double tol, bool zero_guess, mg
                 zx32 = F.f32.x;
                 zt32 = F.f32.t;
             }
-            TRY(vcycle<float>(c, 0, &zx32, &zt32, r32, true, queued ? pre : 0));
+            TRY(vcycle<float>(c, 0, &zx32, &zt32, r32, true, queued ? pre : 0, queued && queued_restricted));
             TRY(fcg_step<float>(c, zx32, x, r32, first, dq_prev));
         } else {
             if (!queued) {
@@ -664,7 +716,7 @@ int fcg_loop(mg_ctx* c, double* x, double bnorm, double tol, bool zero_guess, mg
             if (c->mixed) {
                 zx32 = F.f32.x;
                 zt32 = F.f32.t;
-                TRY(smooth<float>(c, 0, r32, &zx32, &zt32, 0, pre, true));
+                TRY(presmooth<float>(c, 0, r32, &zx32, &zt32, &queued_restricted));
             } else {
                 zx64 = F.f64.x;
                 zt64 = F.f64.t;
@@ -833,13 +885,13 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
         // round trip.  They are skipped when the norm is expected to meet the
         // tolerance: rr_k ~ rr_{k-1}^2 / rr_{k-2}, with a margin of 4.
         const int pre = c->opts.pre;
-        bool queued = false;
+        bool queued = false, queued_restricted = false;
         double rr_before = -1.0;
         float* ex = F0.f32.x;
         float* et = F0.f32.t;
         while (status == MG_ENOCONV && cycles < maxc) {
             if (queued) {
-                TRY(vcycle<float>(c, 0, &ex, &et, r32, true, pre));
+                TRY(vcycle<float>(c, 0, &ex, &et, r32, true, pre, queued_restricted));
             } else {
                 ex = F0.f32.x;
                 et = F0.f32.t;
@@ -856,7 +908,7 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
             if (pre > 0 && cycles < maxc && expect > 4.0 * tol) {
                 ex = F0.f32.x;
                 et = F0.f32.t;
-                TRY(smooth<float>(c, 0, r32, &ex, &et, 0, pre, true));
+                TRY(presmooth<float>(c, 0, r32, &ex, &et, &queued_restricted));
                 queued = true;
             }
             TRY(fetch_scalars_end(c, ready));
@@ -1017,11 +1069,14 @@ int setup_impl(mg_ctx* c, const double* pbx, const double* pby, const double* pb
     Level& F = c->lev[0];
     // up to one face per thread; one partial count of bad faces per block
     const long faces = n_fx(F.d) + n_fy(F.d) + n_fz(F.d);
-    const int nb = (int)std::min<long>((faces + kBlock - 1) / kBlock, kMaxPartials);
+    int nb = (int)std::min<long>((faces + kBlock - 1) / kBlock, kMaxPartials);
     if (rho) {
         HIP_TRY(c, hipMemcpyAsync(c->rho, rho, sizeof(double) * F.n, hipMemcpyDeviceToDevice, c->stream));
-        k_faces_from_density<true><<<nb, kBlock, 0, c->stream>>>(c->rho, F.d, F.f64.bx, F.f64.by, F.f64.bz,
-                                                                 c->partials);
+        const MarchGeom g = march_geom(F.d, kMaxPartials);
+        nb = g.blocks;
+        k_faces_march<<<g.blocks, kMarchTX * kMarchTY, 0, c->stream>>>(
+            DensityFaceOp<true>{c->rho}, F.d, F.d.nx + 2, g.zc, g.ntx, g.nty, g.ntiles, F.f64.bx, F.f64.by, F.f64.bz,
+            c->partials);
     } else {
         k_import_faces<<<nb, kBlock, 0, c->stream>>>(pbx, pby, pbz, F.d, F.f64.bx, F.f64.by, F.f64.bz,
                                                      c->partials);
@@ -1323,9 +1378,10 @@ int mg_face_grad(mg_ctx* c, const double* lambda, const double* p, double* g_x, 
         return MG_EINVAL;
     }
     Level& F = c->lev[0];
-    const long total = (long)F.d.nz * F.d.ny * (F.d.nx + 1) + (long)F.d.nz * (F.d.ny + 1) * F.d.nx +
-                       (long)(F.d.nz + 1) * F.d.ny * F.d.nx;
-    k_face_grad<<<grid_full(total), kBlock, 0, c->stream>>>(lambda, p, F.d, 1.0 / (F.h * F.h), g_x, g_y, g_z);
+    const MarchGeom g = march_geom(F.d, kMaxGridBlocks);
+    k_faces_march<<<g.blocks, kMarchTX * kMarchTY, 0, c->stream>>>(FaceGradOp{lambda, p, 1.0 / (F.h * F.h)}, F.d,
+                                                                    F.d.nx + 1, g.zc, g.ntx, g.nty, g.ntiles, g_x,
+                                                                    g_y, g_z, nullptr);
     CHECK_LAUNCH(c);
     return MG_OK;
 }
@@ -1366,11 +1422,11 @@ int mg_faces_from_vof(const double* f_drop, const double* f_film, const int dims
     if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return MG_EINVAL;
     if (!(rho_drop > 0) || !(rho_film > 0) || !(rho_gas > 0)) return MG_EINVAL;
     const Dims d{dims[0], dims[1], dims[2]};
-    const long total = (long)d.nz * d.ny * (d.nx + 1) + (long)d.nz * (d.ny + 1) * d.nx +
-                       (long)(d.nz + 1) * d.ny * d.nx;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    k_faces_from_vof<<<grid_full(total), kBlock, 0, s>>>(f_drop, f_film, d, rho_drop, rho_film, rho_gas, beta_x,
-                                                        beta_y, beta_z);
+    const MarchGeom g = march_geom(d, kMaxGridBlocks);
+    k_faces_march<<<g.blocks, kMarchTX * kMarchTY, 0, s>>>(VofFaceOp{f_drop, f_film, rho_drop, rho_film, rho_gas}, d,
+                                                            d.nx + 1, g.zc, g.ntx, g.nty, g.ntiles, beta_x, beta_y,
+                                                            beta_z, nullptr);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 
@@ -1392,10 +1448,10 @@ int mg_faces_from_density(const double* rho, const int dims[3], double* beta_x, 
     if (!rho || !dims || !beta_x || !beta_y || !beta_z) return MG_EINVAL;
     if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return MG_EINVAL;
     const Dims d{dims[0], dims[1], dims[2]};
-    const long total = (long)d.nz * d.ny * (d.nx + 1) + (long)d.nz * (d.ny + 1) * d.nx +
-                       (long)(d.nz + 1) * d.ny * d.nx;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    k_faces_from_density<false><<<grid_full(total), kBlock, 0, s>>>(rho, d, beta_x, beta_y, beta_z, nullptr);
+    const MarchGeom g = march_geom(d, kMaxGridBlocks);
+    k_faces_march<<<g.blocks, kMarchTX * kMarchTY, 0, s>>>(DensityFaceOp<false>{rho}, d, d.nx + 1, g.zc, g.ntx,
+                                                            g.nty, g.ntiles, beta_x, beta_y, beta_z, nullptr);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 
@@ -1524,6 +1580,39 @@ int mg_residual_restrict(mg_ctx* c, int level, int precision, const double* b, c
         TRY(convert<double, float>(c, p, L.n, L.f32.x));
         TRY(residual_restrict<float>(c, level, L.f32.b, L.f32.x, C.f32.b));
         TRY(convert<float, double>(c, C.f32.b, C.n, b_coarse));
+    }
+    return MG_OK;
+}
+
+int mg_presmooth_restrict(mg_ctx* c, int level, int precision, const double* b, double* p, double* b_coarse)
+{
+    TRY(check_ctx(c));
+    TRY(level_ok(c, level, precision));
+    if (level >= c->nlev - 1) {
+        set_err(c, "level %d has no coarser level", level);
+        return MG_EINVAL;
+    }
+    if (!b || !p || !b_coarse) {
+        set_err(c, "invalid pre-smoothing arguments");
+        return MG_EINVAL;
+    }
+    Level& L = c->lev[level];
+    Level& C = c->lev[level + 1];
+    bool restricted = false;
+    if (precision == MG_PREC_FP64) {
+        double* x = level == 0 ? c->work : L.f64.x;
+        double* t = level == 0 ? c->ptmp : L.f64.t;
+        TRY(presmooth<double>(c, level, b, &x, &t, &restricted));
+        TRY(residual_restrict<double>(c, level, b, x, b_coarse));
+        HIP_TRY(c, hipMemcpyAsync(p, x, sizeof(double) * L.n, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        float* x = L.f32.x;
+        float* t = L.f32.t;
+        TRY(convert<double, float>(c, b, L.n, L.f32.b));
+        TRY(presmooth<float>(c, level, L.f32.b, &x, &t, &restricted));
+        if (!restricted) TRY(residual_restrict<float>(c, level, L.f32.b, x, C.f32.b));
+        TRY(convert<float, double>(c, C.f32.b, C.n, b_coarse));
+        TRY(convert<float, double>(c, x, L.n, p));
     }
     return MG_OK;
 }

@@ -25,9 +25,15 @@ __device__ inline void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Quotient n/d from the hardware reciprocal: about 1 ulp in FP32; in FP64 the
-// reciprocal is refined by two Newton steps and the quotient by one residual
-// correction (within 1 ulp of the correctly rounded quotient).  d > 0 here.
+// Quotient n/d from the hardware reciprocal.  FP32: n * rcp(d), about 1 ulp
+// and not refined: the FP32 division is that of the smoother of the mixed
+// V-cycle, whose rounding the FP64 defect correction around it removes.  FP64:
+// the reciprocal estimate is refined by two Newton-Raphson steps for 1/d,
+// r <- r + r (1 - d r), and the quotient by one residual correction,
+// q <- q + r (n - d q), each with a fused multiply-add: the iteration of
+// P. Markstein, "Computation of elementary functions on the IBM RISC System/6000
+// processor", IBM J. Res. Develop. 34(1), 1990; within 1 ulp of the correctly
+// rounded quotient.  d > 0 here.
 __device__ __forceinline__ float quot(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
 __device__ __forceinline__ double quot(double n, double d)
 {

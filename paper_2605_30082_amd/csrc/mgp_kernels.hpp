@@ -634,47 +634,6 @@ __global__ void k_outer_update(const double* __restrict__ bx, const double* __re
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-// g_f = (lambda_R - lambda_L)(p_R - p_L)/h^2 on interior faces, 0 on walls (public face layouts)
-__global__ void k_face_grad(const double* __restrict__ lam, const double* __restrict__ p, Dims d, double inv_h2,
-                            double* __restrict__ gx, double* __restrict__ gy, double* __restrict__ gz)
-{
-    const long nfx = (long)d.nz * d.ny * (d.nx + 1);
-    const long nfy = (long)d.nz * (d.ny + 1) * d.nx;
-    const long nfz = (long)(d.nz + 1) * d.ny * d.nx;
-    const long total = nfx + nfy + nfz;
-    const long sz = (long)d.nx * d.ny;
-    for (long f = (long)blockIdx.x * kBlock + threadIdx.x; f < total; f += (long)gridDim.x * kBlock) {
-        if (f < nfx) {
-            const int i = (int)(f % (d.nx + 1));
-            const long row = f / (d.nx + 1);
-            double g = 0.0;
-            if (i > 0 && i < d.nx) {
-                const long c = row * d.nx + i;
-                g = (lam[c] - lam[c - 1]) * (p[c] - p[c - 1]) * inv_h2;
-            }
-            gx[f] = g;
-        } else if (f < nfx + nfy) {
-            const long t = f - nfx;
-            const int i = (int)(t % d.nx);
-            const long r = t / d.nx;
-            const int j = (int)(r % (d.ny + 1));
-            const int k = (int)(r / (d.ny + 1));
-            double g = 0.0;
-            if (j > 0 && j < d.ny) {
-                const long c = ((long)k * d.ny + j) * d.nx + i;
-                g = (lam[c] - lam[c - d.nx]) * (p[c] - p[c - d.nx]) * inv_h2;
-            }
-            gy[t] = g;
-        } else {
-            const long t = f - nfx - nfy;
-            const int k = (int)(t / sz);
-            double g = 0.0;
-            if (k > 0 && k < d.nz) g = (lam[t] - lam[t - sz]) * (p[t] - p[t - sz]) * inv_h2;
-            gz[t] = g;
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // inputs of the solve (contraction off: each product rounds, as written)
 // ---------------------------------------------------------------------------
@@ -687,114 +646,12 @@ __device__ inline double cell_density(double fd, double ff, double rd, double rf
     return rd * fd + rf * ff + rg * fg;
 }
 
-__global__ void k_faces_from_vof(const double* __restrict__ fd, const double* __restrict__ ff, Dims d,
-                                 double rd, double rf, double rg, double* __restrict__ gx,
-                                 double* __restrict__ gy, double* __restrict__ gz)
-{
-#pragma clang fp contract(off)
-    const long nfx = (long)d.nz * d.ny * (d.nx + 1);
-    const long nfy = (long)d.nz * (d.ny + 1) * d.nx;
-    const long nfz = (long)(d.nz + 1) * d.ny * d.nx;
-    const long total = nfx + nfy + nfz;
-    const long sz = (long)d.nx * d.ny;
-    for (long f = (long)blockIdx.x * kBlock + threadIdx.x; f < total; f += (long)gridDim.x * kBlock) {
-        long a = -1, bcell = -1;
-        double* out;
-        long o;
-        if (f < nfx) {
-            const int i = (int)(f % (d.nx + 1));
-            const long row = f / (d.nx + 1);
-            if (i > 0 && i < d.nx) { bcell = row * d.nx + i; a = bcell - 1; }
-            out = gx; o = f;
-        } else if (f < nfx + nfy) {
-            const long t = f - nfx;
-            const int i = (int)(t % d.nx);
-            const long r = t / d.nx;
-            const int j = (int)(r % (d.ny + 1));
-            const int k = (int)(r / (d.ny + 1));
-            if (j > 0 && j < d.ny) { bcell = ((long)k * d.ny + j) * d.nx + i; a = bcell - d.nx; }
-            out = gy; o = t;
-        } else {
-            const long t = f - nfx - nfy;
-            const int k = (int)(t / sz);
-            if (k > 0 && k < d.nz) { bcell = t; a = t - sz; }
-            out = gz; o = t;
-        }
-        double v = 0.0;
-        if (a >= 0) {
-            const double ra = cell_density(fd[a], ff[a], rd, rf, rg);
-            const double rb = cell_density(fd[bcell], ff[bcell], rd, rf, rg);
-            v = 2.0 / (ra + rb);
-        }
-        out[o] = v;
-    }
-}
-
 // rho = sum_i rho_i f_i per cell
 __global__ void k_density_from_vof(const double* __restrict__ fd, const double* __restrict__ ff, long n,
                                    double rd, double rf, double rg, double* __restrict__ rho)
 {
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock)
         rho[i] = cell_density(fd[i], ff[i], rd, rf, rg);
-}
-
-// Face coefficients 2/(rho_L + rho_R) from a cell density, 0 on walls.  PAD
-// writes the internal layouts (x rows nx+2 long, padding 0) and a partial count
-// of interior faces whose coefficient or either density is not finite and > 0;
-// otherwise the public layouts.
-template <bool PAD>
-__global__ void k_faces_from_density(const double* __restrict__ rho, Dims d, double* __restrict__ gx,
-                                     double* __restrict__ gy, double* __restrict__ gz,
-                                     double* __restrict__ partials)
-{
-    const int rx = PAD ? d.nx + 2 : d.nx + 1;
-    const long nfx = (long)d.nz * d.ny * rx;
-    const long nfy = (long)d.nz * (d.ny + 1) * d.nx;
-    const long nfz = (long)(d.nz + 1) * d.ny * d.nx;
-    const long total = nfx + nfy + nfz;
-    const long sz = (long)d.nx * d.ny;
-    double bad = 0.0;
-    // face index arithmetic in U: 32-bit unsigned where every index fits (no
-    // 64-bit divisions), else 64-bit; same faces either way
-    auto run = [&](auto zero) {
-        using U = decltype(zero);
-        const U ux = (U)d.nx, urx = (U)rx, ufx = (U)nfx, ufy = (U)nfy, usz = (U)sz, uyp = (U)d.nx * (U)(d.ny + 1);
-        for (U f = (U)blockIdx.x * kBlock + threadIdx.x; f < (U)total; f += (U)gridDim.x * kBlock) {
-            long a = -1, bcell = -1;
-            double* out;
-            U o;
-            if (f < ufx) {
-                const U row = f / urx;
-                const int i = (int)(f - row * urx);
-                if (i > 0 && i < d.nx) { bcell = (long)(row * ux) + i; a = bcell - 1; }
-                out = gx; o = f;
-            } else if (f < ufx + ufy) {
-                const U t = f - ufx;
-                const U k = t / uyp, rest = t - k * uyp;
-                const U j = rest / ux, i = rest - j * ux;
-                if (j > 0 && j < (U)d.ny) { bcell = (long)((k * (U)d.ny + j) * ux + i); a = bcell - d.nx; }
-                out = gy; o = t;
-            } else {
-                const U t = f - ufx - ufy;
-                const U k = t / usz;
-                if (k > 0 && k < (U)d.nz) { bcell = (long)t; a = (long)(t - usz); }
-                out = gz; o = t;
-            }
-            double v = 0.0;
-            if (a >= 0) {
-                const double ra = rho[a], rb = rho[bcell];
-                v = 2.0 / (ra + rb);
-                bad += (bad_coeff(v) || bad_coeff(ra) || bad_coeff(rb)) ? 1.0 : 0.0;
-            }
-            out[o] = v;
-        }
-    };
-    if (total + (long)gridDim.x * kBlock < (1L << 32)) run(0u);
-    else run(0ul);
-    if (PAD) {
-        bad = block_sum(bad);
-        if (threadIdx.x == 0) partials[blockIdx.x] = bad;
-    }
 }
 
 __global__ void k_divergence(const double* __restrict__ u, const double* __restrict__ v,

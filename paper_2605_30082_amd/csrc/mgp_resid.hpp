@@ -245,19 +245,22 @@ k_resid(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict_
         const T2 nn = *reinterpret_cast<const T2*>(S0 + li + kResEX);
         const T2 dn = *reinterpret_cast<const T2*>(Sm + li);
         const T2 up = *reinterpret_cast<const T2*>(Sp + li);
-        // cell 0 (even x): west w, east c.y; cell 1: west c.x, east ea
+        // cell 0 (even x): west w, east c.y; cell 1: west c.x, east ea.  The
+        // products accumulate through explicit fmas in this order (contraction
+        // may fuse either product of a two-product sum; the FP32 pre-smoothing +
+        // restriction kernel rounds its residuals exactly like this)
         T dg0 = C.bx.x, of0 = C.bx.x * w;
-        dg0 += C.bx.y; of0 += C.bx.y * c.y;
-        dg0 += C.by.x; of0 += C.by.x * sn.x;
-        dg0 += C.byu.x; of0 += C.byu.x * nn.x;
-        dg0 += bzl.x; of0 += bzl.x * dn.x;
-        dg0 += C.bzh.x; of0 += C.bzh.x * up.x;
+        dg0 += C.bx.y; of0 = fma(C.bx.y, c.y, of0);
+        dg0 += C.by.x; of0 = fma(C.by.x, sn.x, of0);
+        dg0 += C.byu.x; of0 = fma(C.byu.x, nn.x, of0);
+        dg0 += bzl.x; of0 = fma(bzl.x, dn.x, of0);
+        dg0 += C.bzh.x; of0 = fma(C.bzh.x, up.x, of0);
         T dg1 = C.bx.y, of1 = C.bx.y * c.x;
-        dg1 += C.bxn; of1 += C.bxn * ea;
-        dg1 += C.by.y; of1 += C.by.y * sn.y;
-        dg1 += C.byu.y; of1 += C.byu.y * nn.y;
-        dg1 += bzl.y; of1 += bzl.y * dn.y;
-        dg1 += C.bzh.y; of1 += C.bzh.y * up.y;
+        dg1 += C.bxn; of1 = fma(C.bxn, ea, of1);
+        dg1 += C.by.y; of1 = fma(C.by.y, sn.y, of1);
+        dg1 += C.byu.y; of1 = fma(C.byu.y, nn.y, of1);
+        dg1 += bzl.y; of1 = fma(bzl.y, dn.y, of1);
+        dg1 += C.bzh.y; of1 = fma(C.bzh.y, up.y, of1);
         const T r0 = mine ? C.b.x - (of0 - dg0 * c.x) * inv_h2 : (T)0;
         const T r1 = mine ? C.b.y - (of1 - dg1 * c.y) * inv_h2 : (T)0;
         const long cell = (long)s * d.nx * d.ny + (long)y * d.nx + xp;

@@ -217,12 +217,14 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         const T bzl = odd ? C.bz.y : C.bz.x;
         const T bzh = odd ? Cup.bz.y : Cup.bz.x;
         const T b = odd ? C.b.y : C.b.x;
+        // the products accumulate through explicit fmas in this order (the
+        // pre-smoothing + restriction kernel and the residual pass round alike)
         T dg = bxl, of = bxl * P0[xm];
-        dg += bxh; of += bxh * P0[xm + 1];
-        dg += byl; of += byl * P0[li - G::RS];
-        dg += byh; of += byh * P0[li + G::RS];
-        dg += bzl; of += bzl * Pm[li];
-        dg += bzh; of += bzh * Pp[li];
+        dg += bxh; of = fma(bxh, P0[xm + 1], of);
+        dg += byl; of = fma(byl, P0[li - G::RS], of);
+        dg += byh; of = fma(byh, P0[li + G::RS], of);
+        dg += bzl; of = fma(bzl, Pm[li], of);
+        dg += bzh; of = fma(bzh, Pp[li], of);
         v = quot(of - h2 * b, dg);
     };
 

@@ -266,6 +266,17 @@ class Solver:
                                                    _ptr(out, "b_coarse")))
         return out
 
+    def presmooth_restrict(self, b: torch.Tensor, level: int = 0, precision: str = "fp64"):
+        """The V-cycle's pre-smoothing of `level` from zero and the restriction of
+        its residual: returns (p, b_coarse)."""
+        shp = self._level_shape(level)
+        p = torch.empty(shp, dtype=torch.float64, device=b.device)
+        out = torch.empty(self._level_shape(level + 1), dtype=torch.float64, device=b.device)
+        pr = L.MG_PREC_FP64 if precision == "fp64" else L.MG_PREC_MIXED
+        self._check(self._lib.mg_presmooth_restrict(self._ctx, level, pr, _ptr(b, "b", shp), _ptr(p, "p", shp),
+                                                    _ptr(out, "b_coarse")))
+        return p, out
+
     def prolong_correct(self, e: torch.Tensor, p: torch.Tensor, level: int = 0,
                         precision: str = "fp64") -> torch.Tensor:
         q = p.clone()

@@ -40,7 +40,7 @@ def test_enum_values_match_header():
     for name in ("MG_OK", "MG_EINVAL", "MG_ENOMEM", "MG_EHIP", "MG_ENOCONV", "MG_ENONFINITE",
                  "MG_BC_NEUMANN", "MG_PREC_FP64", "MG_PREC_MIXED", "MG_FLAG_ZERO_GUESS",
                  "MG_FLAG_TIMING", "MG_FLAG_FCG", "MG_FLAG_LEVEL_LAUNCHES", "MG_K_SWEEP", "MG_K_RESTRICT", "MG_K_PROLONG", "MG_K_OUTER",
-                 "MG_K_NORM", "MG_K_SWEEP2", "MG_K_COUNT"):
+                 "MG_K_NORM", "MG_K_SWEEP2", "MG_K_SWEEP2R", "MG_K_COUNT"):
         m = re.search(rf"\b{name}\s*=\s*(-?\d+)", text)
         assert m, name
         assert int(m.group(1)) == getattr(L, name), name

@@ -55,3 +55,16 @@ def test_more_than_one_gpu_is_refused():
     assert out.returncode == 2
     msg = json.loads(out.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "single-GPU" in msg["error"]
+
+
+def test_cpu_baseline_runs_the_whole_oracle_solve_and_reports_the_host():
+    from paper_2605_30082_amd import workloads as W
+    wl = W.make("sphere", 16)
+    cpu = bench.cpu_baseline(wl, parse("--workload", "sphere", "--n", "16"), 9)
+    assert cpu["kind"] == "oracle" and cpu["unit"] == "ms" and cpu["value"] > 0
+    assert cpu["rel_res"] <= 1e-10 and 5 <= cpu["cycles"] <= 30
+    assert cpu["cores"] >= 1 and cpu["single_thread_one_cycle_s"] > 0
+    host = cpu["host"]
+    assert host["logical_cpus_usable"] >= 1
+    if cpu["peak_rss_gib"] is not None:
+        assert cpu["peak_rss_gib"] >= cpu["rss_before_gib"] > 0

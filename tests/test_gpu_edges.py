@@ -136,8 +136,10 @@ def test_kernel_timing_stats(density):
         if precision == "mixed":
             # at 64^3 only the finest grid is wide enough for the tiled kernels
             # (from p = 0 the initial residual is the rhs itself: no outer update before cycle 1;
-            # the post-smoothing's first two-sweep launch does the prolongation itself)
-            expect = {L.MG_K_SWEEP2: 2 * n, L.MG_K_RESTRICT: n, L.MG_K_PROLONG: 0, L.MG_K_OUTER: n}
+            # the pre-smoothing launch also restricts the residual, the post-smoothing's
+            # first two-sweep launch does the prolongation itself)
+            expect = {L.MG_K_SWEEP2R: n, L.MG_K_SWEEP2: n, L.MG_K_RESTRICT: 0, L.MG_K_PROLONG: 0,
+                      L.MG_K_OUTER: n}
         else:
             # the first cycle runs both pre-sweeps; every later one starts with the
             # sweep that also takes the norm of the previous result, and so does the
@@ -145,9 +147,9 @@ def test_kernel_timing_stats(density):
             expect = {L.MG_K_SWEEP: 3 * n + 1, L.MG_K_NORM: n, L.MG_K_RESTRICT: n, L.MG_K_PROLONG: n}
         # (mixed) the next cycle's pre-sweeps are queued while the host waits for a
         # norm; one such launch may run in vain after the last cycle
-        spare = 1 if precision == "mixed" and st.kernel_launches[L.MG_K_SWEEP2] == 2 * n + 1 else 0
+        spare = 1 if precision == "mixed" and st.kernel_launches[L.MG_K_SWEEP2R] == n + 1 else 0
         if spare:
-            expect[L.MG_K_SWEEP2] += 1
+            expect[L.MG_K_SWEEP2R] += 1
         for k, count in expect.items():
             assert st.kernel_launches[k] == count, (precision, k, st.kernel_launches[k], count)
             assert st.kernel_launches_finest[k] == count
@@ -157,7 +159,7 @@ def test_kernel_timing_stats(density):
         assert sum(st0.kernel_launches) == 0
         # a class mask: only the selected class is timed, results unchanged
         with make(precision=precision, zero_guess=True, timing=True) as s:
-            only = L.MG_K_RESTRICT
+            only = L.MG_K_SWEEP2R if precision == "mixed" else L.MG_K_RESTRICT
             s.set_timing_classes([only])
             p2, st2 = s.solve(gd, 1e-10)
             assert torch.equal(p2, p0)
@@ -218,14 +220,16 @@ def test_mixed_zero_guess_without_cycles(density):
 
 
 @pytest.mark.parametrize("dims", [(8, 8, 8), (16, 16, 16), (8, 16, 32), (12, 8, 16), (32, 32, 32), (96, 96, 96),
-                                  (128, 64, 32), (64, 64, 16)])
+                                  (128, 64, 32), (64, 64, 16), (96, 96, 128)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("method", ["vcycle", "fcg"])
 def test_fused_launches_match_level_launches(dims, precision, method):
     """By default the levels of at most 4096 cells run as one single-workgroup
-    launch and (mixed) the post-smoothing's two-sweep launch prolongates the
-    coarse correction itself; with level_launches=True every step is its own
-    launch.  Same values in the same order: identical solutions and histories."""
+    launch and (mixed) the pre-smoothing's two-sweep launch also restricts its
+    residual and the post-smoothing's two-sweep launch prolongates the coarse
+    correction itself; with level_launches=True every step is its own launch.
+    Same values in the same order: identical solutions and histories.
+    (96, 96, 128): ragged last x-tile and z-chunk of the pre-smoothing launch."""
     nx, ny, nz = dims
     beta = random_beta(dims, 41)
     h = 1.0 / max(dims)
@@ -285,3 +289,45 @@ def test_queued_presweeps_never_change_the_result(method):
         assert st_tol.cycles == k and st_max.cycles == k
         assert st_tol.hist == st_max.hist == full.hist[:k + 1]
         assert torch.equal(p_tol, p_max)
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (1, 5, 3), (70, 3, 130), (130, 9, 2), (64, 4, 64), (3, 200, 7)])
+def test_face_passes_on_odd_shapes(dims):
+    """The z-marching face kernels (coefficients from the VOF fractions or from
+    a density; the face gradient): single cells and columns, a ragged last
+    x-tile, fewer rows than a block, one-plane z-chunks, rows beyond one block:
+    bit-exact with the oracle."""
+    nx, ny, nz = dims
+    note(f"face passes dims={dims}")
+    g = np.random.default_rng(61)
+    fd = g.uniform(0, 1, (nz, ny, nx))
+    ff = g.uniform(0, 1, (nz, ny, nx)) * (1.0 - fd)
+    gb = S.faces_from_vof(T(fd), T(ff), 1000.0, 960.0, 1.2)
+    ob = oracle.faces_from_vof(fd, ff, 1000.0, 960.0, 1.2)
+    for a, r in zip(gb, ob):
+        np.testing.assert_array_equal(N(a), r)
+    rho = oracle.density(fd, ff, 1000.0, 960.0, 1.2)
+    for a, r in zip(S.faces_from_density(T(rho)), oracle.face_coeffs(rho)):
+        np.testing.assert_array_equal(N(a), r)
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (3, 3, 3), (12, 4, 8), (96, 32, 32), (4, 1, 2)])
+def test_face_grad_on_odd_shapes(dims):
+    """mg_face_grad on grids a context accepts, down to one cell: the oracle's
+    (lambda_R - lambda_L)(p_R - p_L)/h^2 to the rounding of a division against
+    a product with 1/h^2 (h = 1/96, 1/3, ... are not powers of 2), walls 0; a
+    density context (faces formed by the same kernel, with its count of bad
+    faces) equals a face context bit for bit."""
+    nx, ny, nz = dims
+    g = np.random.default_rng(62)
+    rho = g.uniform(1.0, 1000.0, (nz, ny, nx))
+    h = 1.0 / max(dims)
+    lam, p = g.standard_normal((nz, ny, nx)), g.standard_normal((nz, ny, nx))
+    with S.Solver(*[T(a) for a in oracle.face_coeffs(rho)], h) as s:
+        got = s.face_grad(T(lam), T(p))
+        for a, r in zip(got, oracle.face_grad(lam, p, h)):
+            np.testing.assert_allclose(N(a), r, rtol=1e-15, atol=1e-300)
+        faces = [N(a) for a in s.level_faces(0)]
+    with S.Solver.from_density(T(rho), h) as sd:
+        for a, r in zip(sd.level_faces(0), faces):
+            np.testing.assert_array_equal(N(a), r)

@@ -13,6 +13,7 @@ are compared cycle by cycle.  Floating-point tolerances:
 """
 import numpy as np
 import pytest
+import torch
 
 import oracle
 import refs
@@ -179,6 +180,45 @@ def test_smooth_fp32_sweep_pairs(dims):
                     ref = oracle.rbgs_half(lb, b, ref, h, c)
             assert max_rel(got, ref) < 2e-6, (order, sweeps, max_rel(got, ref))
     s.close()
+
+
+# The V-cycle's pre-smoothing from zero with the restriction of its residual.
+# In FP32 grids of at least 64 x 16 cells with even extents take one launch for
+# both (mgp_sweep2r.hpp); (96, 64, 32) has a ragged last x-tile, (96, 96, 128)
+# also a ragged last z-chunk (chunks of 6 planes), (64, 16, 64) many z-chunks of
+# 2 planes (a valid hierarchy makes ny a multiple of the 16-row tile wherever
+# nx >= 64, so no y-tile is ragged); every level of the hierarchy is checked
+# (the coarser ones run the separate passes).
+@pytest.mark.parametrize("dims", [(64, 32, 48), (96, 64, 32), (96, 96, 128), (128, 64, 64), (64, 16, 64)])
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_presmooth_restrict(dims, precision):
+    note(f"presmooth+restrict dims={dims} {precision}")
+    beta = random_beta(dims, 21)
+    h = 1.0 / dims[0]
+    s = make_solver(beta, h, precision=precision)
+    sl = make_solver(beta, h, precision=precision, level_launches=True)
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    for lev in range(s.num_levels - 1):
+        (d, hl) = s.level_info(lev)
+        lb = [N(a) for a in s.level_faces(lev)]
+        b = random_cells(d, 22 + lev)
+        p, bc = s.presmooth_restrict(T(b), level=lev, precision=precision)
+        ref = np.zeros_like(b)
+        for c in (0, 1, 0, 1):
+            ref = oracle.rbgs_half(lb, b, ref, hl, c)
+        assert max_rel(N(p), ref) < tol, (lev, max_rel(N(p), ref))
+        # the restriction of the residual of the iterate the GPU produced ...
+        got_c = N(bc)
+        ref_c = oracle.restrict(oracle.residual(lb, b, N(p), hl))
+        assert max_rel(got_c, ref_c) < 10 * tol, (lev, max_rel(got_c, ref_c))
+        # ... and of the oracle's own iterate
+        ref_c2 = oracle.restrict(oracle.residual(lb, b, ref, hl))
+        assert max_rel(got_c, ref_c2) < 20 * tol, (lev, max_rel(got_c, ref_c2))
+        # one launch or the separate passes: the same numbers bit for bit
+        p2, bc2 = sl.presmooth_restrict(T(b), level=lev, precision=precision)
+        assert torch.equal(p, p2) and torch.equal(bc, bc2), lev
+    s.close()
+    sl.close()
 
 
 @pytest.mark.parametrize("dims", [d for d in DIMS if d != (4, 4, 4)])

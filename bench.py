@@ -43,6 +43,7 @@ SWEEPS_PER_LAUNCH = {"sweep": 1, "sweep2": 2, "sweep2_restrict": 2}
 KERNEL_SYMBOLS = {
     ("sweep", "mixed"): "mgp::k_sweep_fused<float, 8, false>",
     ("sweep", "fp64"): "mgp::k_sweep_fused<double, 16, false>",
+    ("sweep2", "fp64"): "mgp::k_sweep2_fused<double, 64, 8>",
     ("sweep2", "mixed"): "mgp::k_sweep2_fused<float, 64, 16>",
     ("sweep2_restrict", "mixed"): "mgp::k_sweep2_restrict<16>",
     ("residual_restrict", "mixed"): "mgp::k_resid<float, 1, false>",
@@ -50,7 +51,7 @@ KERNEL_SYMBOLS = {
     ("prolong_correct", "mixed"): "mgp::k_prolong_tiled<float>",
     ("prolong_correct", "fp64"): "mgp::k_prolong_tiled<double>",
     ("outer_update", "mixed"): "mgp::k_resid<double, 2, {rho}>",
-    ("residual_norm", "fp64"): "mgp::k_sweep_fused<double, 8, true>",
+    ("residual_norm", "fp64"): "mgp::k_resid<double, 0, {rho}>",
 }
 
 
@@ -251,8 +252,9 @@ def probe_smoothers(args) -> int:
     mg_smooth and mg_presmooth_restrict, on the workload's density field: three
     FP32 two-sweep launches (k_sweep2_fused<float, 64, 16>, from a non-zero
     iterate), three FP32 pre-smoothing launches from zero that also restrict the
-    residual (k_sweep2_restrict<16>) and three FP64 one-sweep launches
-    (k_sweep_fused<double, 16, false>).  The entry points also cast their FP64
+    residual (k_sweep2_restrict<16>), three FP64 one-sweep launches
+    (k_sweep_fused<double, 16, false>) and three FP64 two-sweep launches
+    (k_sweep2_fused<double, 64, 8>).  The entry points also cast their FP64
     arguments to the context's FP32 copies and back (k_convert launches).
     Prints one JSON line of HIP-event times around each call."""
     import numpy as np
@@ -274,7 +276,7 @@ def probe_smoothers(args) -> int:
     b = S.divergence(T(wl.u), T(wl.v), T(wl.w), wl.h, wl.dt)
     b -= b.mean()
     out = {"probe": "smoothers", "n": wl.dims[0]}
-    for name, prec in (("sweep2", "mixed"), ("sweep2_restrict", "mixed"), ("sweep64", "fp64")):
+    for name, prec in (("sweep2", "mixed"), ("sweep2_restrict", "mixed"), ("sweep64", "fp64"), ("sweep2_64", "fp64")):
         with S.Solver.from_density(rho, wl.h, precision=prec) as s:
             p = b.clone()
             times = []
@@ -284,7 +286,7 @@ def probe_smoothers(args) -> int:
                 if name == "sweep2_restrict":
                     p, _ = s.presmooth_restrict(b, level=0, precision=prec)
                 else:
-                    p = s.smooth(b, p, level=0, sweeps=2 if name == "sweep2" else 1, precision=prec)
+                    p = s.smooth(b, p, level=0, sweeps=1 if name == "sweep64" else 2, precision=prec)
                 e1.record()
                 torch.cuda.synchronize()
                 times.append(e0.elapsed_time(e1))

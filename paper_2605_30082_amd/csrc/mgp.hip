@@ -290,20 +290,20 @@ int sweep(mg_ctx* c, int l, const T* b, const T* in, T* out, int order, bool zer
     return MG_OK;
 }
 
-// Two sweeps of one order in one launch (FP32 grids that sweep2_ok accepts);
-// with ec, from in + P ec (the coarse correction of level l + 1 prolongated on
-// the fly).
-int sweep_pair(mg_ctx* c, int l, const float* b, const float* in, float* out, int order, bool zero_in,
-               const float* ec = nullptr)
+// Two sweeps of one order in one launch (grids that sweep2_ok accepts); with
+// ec, from in + P ec (the coarse correction of level l + 1 prolongated on the
+// fly).
+template <typename T>
+int sweep_pair(mg_ctx* c, int l, const T* b, const T* in, T* out, int order, bool zero_in, const T* ec = nullptr)
 {
     Level& L = c->lev[l];
-    LevelBufs<float>& B = L.f32;
+    LevelBufs<T>& B = bufs<T>(L);
     // algorithmic bytes of the work done: two sweeps, plus (ec) the prolongation + correction pass it replaces
-    const double bytes = 2.0 * (double)L.n * sweep_bytes_per_cell<float>() +
-                         (ec ? (double)L.n * (2.0 + 1.0 / 8.0) * sizeof(float) : 0.0);
+    const double bytes = 2.0 * (double)L.n * sweep_bytes_per_cell<T>() +
+                         (ec ? (double)L.n * (2.0 + 1.0 / 8.0) * sizeof(T) : 0.0);
     TimedLaunch tl(c, l, MG_K_SWEEP2, bytes, sweep2_wide(L.d));
-    const hipError_t e = launch_sweep2<float>(B.bx, B.by, B.bz, L.d, (float)(L.h * L.h), b, in, out, order,
-                                              zero_in, c->stream, tl.start(), tl.stop(), ec);
+    const hipError_t e = launch_sweep2<T>(B.bx, B.by, B.bz, L.d, (T)(L.h * L.h), b, in, out, order, zero_in,
+                                          c->stream, tl.start(), tl.stop(), ec);
     if (e != hipSuccess) {
         set_err(c, "sweep launch failed: %s", hipGetErrorString(e));
         return MG_EHIP;
@@ -340,19 +340,17 @@ bool fused_restrict(const mg_ctx* c, int l)
 }
 
 // `count` sweeps of one order on level l from *x (zero_in: from 0) with *t as
-// the ping-pong partner; on return *x holds the result.  FP32 pairs of sweeps
-// run in the two-sweep kernel where the grid allows it.
+// the ping-pong partner; on return *x holds the result.  Pairs of sweeps run
+// in the two-sweep kernel where the grid allows it.
 template <typename T>
 int smooth(mg_ctx* c, int l, const T* b, T** x, T** t, int order, int count, bool zero_in)
 {
     int done = 0;
-    if constexpr (sizeof(T) == 4) {
-        if (sweep2_ok(c->lev[l].d, sizeof(T))) {
-            for (; count - done >= 2; done += 2) {
-                const int e = sweep_pair(c, l, b, *x, *t, order, zero_in && done == 0);
-                if (e != MG_OK) return e;
-                std::swap(*x, *t);
-            }
+    if (sweep2_ok(c->lev[l].d, sizeof(T))) {
+        for (; count - done >= 2; done += 2) {
+            const int e = sweep_pair<T>(c, l, b, *x, *t, order, zero_in && done == 0);
+            if (e != MG_OK) return e;
+            std::swap(*x, *t);
         }
     }
     for (; done < count; ++done) {
@@ -511,13 +509,11 @@ int vcycle(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init, int pre_d
     T* cx = CB.x;
     T* ct = CB.t;
     TRY(vcycle<T>(c, l + 1, &cx, &ct, CB.b, true));
-    if constexpr (sizeof(T) == 4) {
-        // the first two-sweep launch of the post-smoothing adds the prolongated correction itself
-        if (post >= 2 && sweep2_ok(L.d, sizeof(T)) && !(c->opts.flags & MG_FLAG_LEVEL_LAUNCHES)) {
-            TRY(sweep_pair(c, l, b, *x, *t, 1, false, cx));
-            std::swap(*x, *t);
-            return smooth<T>(c, l, b, x, t, 1, post - 2, false);
-        }
+    // the first two-sweep launch of the post-smoothing adds the prolongated correction itself
+    if (post >= 2 && sweep2_ok(L.d, sizeof(T)) && !(c->opts.flags & MG_FLAG_LEVEL_LAUNCHES)) {
+        TRY(sweep_pair<T>(c, l, b, *x, *t, 1, false, cx));
+        std::swap(*x, *t);
+        return smooth<T>(c, l, b, x, t, 1, post - 2, false);
     }
     TRY(prolong_correct<T>(c, l, cx, *x));
     TRY(smooth<T>(c, l, b, x, t, 1, post, false));
@@ -825,7 +821,10 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
         // the next cycle (it reads exactly the residual's inputs): one pass
         // fewer per cycle; when the norm says stop, that sweep's output is
         // dropped.  Grids the fused sweep does not cover use a separate pass.
-        const bool fuse = c->opts.pre > 0 && sweep_is_fused(c->lev[0].d, sizeof(double)) &&
+        // Where the pre-sweeps run as pairs in the two-sweep kernel, an even count
+        // of them stays in pairs and the norm takes a residual pass of its own.
+        const bool pairs = sweep2_ok(c->lev[0].d, sizeof(double)) && c->opts.pre % 2 == 0;
+        const bool fuse = c->opts.pre > 0 && !pairs && sweep_is_fused(c->lev[0].d, sizeof(double)) &&
                           fused_geom<8>(c->lev[0].d).blocks <= kMaxPartials;
         bool known = zero_guess;  // the rr of the current iterate is known (1 for p = 0)
         bool swept = false;       // the next cycle's first pre-sweep has run (into `other`)
@@ -1033,7 +1032,8 @@ int tail_start(const mg_ctx* c)
     for (int l = c->nlev - 1; l >= 0; --l) {
         const Dims& d = c->lev[l].d;
         const bool simple = c->lev[l].n <= kTailCells && !sweep_is_fused(d, 4) && !sweep_is_fused(d, 8) &&
-                            !sweep2_ok(d, 4) && !res_tiled_ok(d, 4) && !res_tiled_ok(d, 8) && !pro_tiled_ok(d, 4) &&
+                            !sweep2_ok(d, 4) && !sweep2_ok(d, 8) && !res_tiled_ok(d, 4) && !res_tiled_ok(d, 8) &&
+                            !pro_tiled_ok(d, 4) &&
                             !pro_tiled_ok(d, 8);
         if (!simple) break;
         l0 = l;
@@ -1070,16 +1070,21 @@ int setup_impl(mg_ctx* c, const double* pbx, const double* pby, const double* pb
     // up to one face per thread; one partial count of bad faces per block
     const long faces = n_fx(F.d) + n_fy(F.d) + n_fz(F.d);
     int nb = (int)std::min<long>((faces + kBlock - 1) / kBlock, kMaxPartials);
+    // every level's FP32 coefficient copies (mixed precision) are written by the
+    // pass that forms the FP64 ones
+    float* f32x = c->mixed ? F.f32.bx : nullptr;
+    float* f32y = c->mixed ? F.f32.by : nullptr;
+    float* f32z = c->mixed ? F.f32.bz : nullptr;
     if (rho) {
-        HIP_TRY(c, hipMemcpyAsync(c->rho, rho, sizeof(double) * F.n, hipMemcpyDeviceToDevice, c->stream));
+        // the pass that forms the faces also keeps the context's copy of rho
         const MarchGeom g = march_geom(F.d, kMaxPartials);
         nb = g.blocks;
         k_faces_march<<<g.blocks, kMarchTX * kMarchTY, 0, c->stream>>>(
-            DensityFaceOp<true>{c->rho}, F.d, F.d.nx + 2, g.zc, g.ntx, g.nty, g.ntiles, F.f64.bx, F.f64.by, F.f64.bz,
-            c->partials);
+            DensityFaceOp<true>{rho, c->rho}, F.d, F.d.nx + 2, g.zc, g.ntx, g.nty, g.ntiles, F.f64.bx, F.f64.by,
+            F.f64.bz, c->partials, f32x, f32y, f32z);
     } else {
-        k_import_faces<<<nb, kBlock, 0, c->stream>>>(pbx, pby, pbz, F.d, F.f64.bx, F.f64.by, F.f64.bz,
-                                                     c->partials);
+        k_import_faces<<<nb, kBlock, 0, c->stream>>>(pbx, pby, pbz, F.d, F.f64.bx, F.f64.by, F.f64.bz, c->partials,
+                                                     f32x, f32y, f32z);
     }
     c->use_rho = rho != nullptr;
     CHECK_LAUNCH(c);
@@ -1088,18 +1093,10 @@ int setup_impl(mg_ctx* c, const double* pbx, const double* pby, const double* pb
         Level& A = c->lev[l - 1];
         Level& B = c->lev[l];
         const long nf = n_fx(B.d) + n_fy(B.d) + n_fz(B.d);
-        k_coarsen_faces<<<grid_full(nf), kBlock, 0, c->stream>>>(A.f64.bx, A.f64.by, A.f64.bz, A.d, B.d,
-                                                                B.f64.bx, B.f64.by, B.f64.bz);
+        k_coarsen_faces<<<grid_full(nf), kBlock, 0, c->stream>>>(
+            A.f64.bx, A.f64.by, A.f64.bz, A.d, B.d, B.f64.bx, B.f64.by, B.f64.bz, c->mixed ? B.f32.bx : nullptr,
+            c->mixed ? B.f32.by : nullptr, c->mixed ? B.f32.bz : nullptr);
         CHECK_LAUNCH(c);
-    }
-    if (c->mixed) {
-        for (int l = 0; l < c->nlev; ++l) {
-            Level& L = c->lev[l];
-            k_convert<double, float><<<grid_full(n_fx(L.d)), kBlock, 0, c->stream>>>(L.f64.bx, n_fx(L.d), L.f32.bx);
-            k_convert<double, float><<<grid_full(n_fy(L.d)), kBlock, 0, c->stream>>>(L.f64.by, n_fy(L.d), L.f32.by);
-            k_convert<double, float><<<grid_full(n_fz(L.d)), kBlock, 0, c->stream>>>(L.f64.bz, n_fz(L.d), L.f32.bz);
-            CHECK_LAUNCH(c);
-        }
     }
     Level& Cl = c->lev[c->nlev - 1];
     k_coarse_inverse<<<1, kCoarseNT, 0, c->stream>>>(Cl.f64.bx, Cl.f64.by, Cl.f64.bz, Cl.d, Cl.h, c->G,
@@ -1450,7 +1447,7 @@ int mg_faces_from_density(const double* rho, const int dims[3], double* beta_x, 
     const Dims d{dims[0], dims[1], dims[2]};
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     const MarchGeom g = march_geom(d, kMaxGridBlocks);
-    k_faces_march<<<g.blocks, kMarchTX * kMarchTY, 0, s>>>(DensityFaceOp<false>{rho}, d, d.nx + 1, g.zc, g.ntx,
+    k_faces_march<<<g.blocks, kMarchTX * kMarchTY, 0, s>>>(DensityFaceOp<false>{rho, nullptr}, d, d.nx + 1, g.zc, g.ntx,
                                                             g.nty, g.ntiles, beta_x, beta_y, beta_z, nullptr);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }

@@ -147,8 +147,10 @@ __device__ inline bool bad_coeff(double v)
 __global__ void k_import_faces(const double* __restrict__ pbx, const double* __restrict__ pby,
                                const double* __restrict__ pbz, Dims d, double* __restrict__ bx,
                                double* __restrict__ by, double* __restrict__ bz,
-                               double* __restrict__ partials)
+                               double* __restrict__ partials, float* __restrict__ fbx = nullptr,
+                               float* __restrict__ fby = nullptr, float* __restrict__ fbz = nullptr)
 {
+    const bool f32 = fbx != nullptr;  // also the FP32 copies (all three or none)
     const long nx_ = n_fx(d), ny_ = n_fy(d), nz_ = n_fz(d);
     const long total = nx_ + ny_ + nz_;
     double bad = 0.0;
@@ -162,6 +164,7 @@ __global__ void k_import_faces(const double* __restrict__ pbx, const double* __r
                 bad += bad_coeff(v) ? 1.0 : 0.0;
             }
             bx[f] = v;
+            if (f32) fbx[f] = (float)v;
         } else if (f < nx_ + ny_) {
             const long g = f - nx_;
             const int y = (int)((g / d.nx) % (d.ny + 1));
@@ -171,6 +174,7 @@ __global__ void k_import_faces(const double* __restrict__ pbx, const double* __r
                 bad += bad_coeff(v) ? 1.0 : 0.0;
             }
             by[g] = v;
+            if (f32) fby[g] = (float)v;
         } else {
             const long g = f - nx_ - ny_;
             const int z = (int)(g / ((long)d.ny * d.nx));
@@ -180,6 +184,7 @@ __global__ void k_import_faces(const double* __restrict__ pbx, const double* __r
                 bad += bad_coeff(v) ? 1.0 : 0.0;
             }
             bz[g] = v;
+            if (f32) fbz[g] = (float)v;
         }
     }
     bad = block_sum(bad);
@@ -211,8 +216,10 @@ __global__ void k_export_faces(const T* __restrict__ bx, const T* __restrict__ b
 // coarse face = mean of the 4 fine faces that tile it (walls stay 0)
 __global__ void k_coarsen_faces(const double* __restrict__ fbx, const double* __restrict__ fby,
                                 const double* __restrict__ fbz, Dims f, Dims c, double* __restrict__ cbx,
-                                double* __restrict__ cby, double* __restrict__ cbz)
+                                double* __restrict__ cby, double* __restrict__ cbz, float* __restrict__ sbx = nullptr,
+                                float* __restrict__ sby = nullptr, float* __restrict__ sbz = nullptr)
 {
+    const bool f32 = sbx != nullptr;  // also the FP32 copies (all three or none)
     const long nx_ = n_fx(c), ny_ = n_fy(c), nz_ = n_fz(c);
     const long total = nx_ + ny_ + nz_;
     for (long g = (long)blockIdx.x * kBlock + threadIdx.x; g < total; g += (long)gridDim.x * kBlock) {
@@ -225,6 +232,7 @@ __global__ void k_coarsen_faces(const double* __restrict__ fbx, const double* __
                 v = (fbx[fx_index(f, 2 * X, 2 * Y, 2 * Z)] + fbx[fx_index(f, 2 * X, 2 * Y + 1, 2 * Z)] +
                      fbx[fx_index(f, 2 * X, 2 * Y, 2 * Z + 1)] + fbx[fx_index(f, 2 * X, 2 * Y + 1, 2 * Z + 1)]) / 4.0;
             cbx[g] = v;
+            if (f32) sbx[g] = (float)v;
         } else if (g < nx_ + ny_) {
             const long h = g - nx_;
             const int X = (int)(h % c.nx);
@@ -235,6 +243,7 @@ __global__ void k_coarsen_faces(const double* __restrict__ fbx, const double* __
                 v = (fby[fy_index(f, 2 * X, 2 * Y, 2 * Z)] + fby[fy_index(f, 2 * X + 1, 2 * Y, 2 * Z)] +
                      fby[fy_index(f, 2 * X, 2 * Y, 2 * Z + 1)] + fby[fy_index(f, 2 * X + 1, 2 * Y, 2 * Z + 1)]) / 4.0;
             cby[h] = v;
+            if (f32) sby[h] = (float)v;
         } else {
             const long h = g - nx_ - ny_;
             const int X = (int)(h % c.nx);
@@ -245,6 +254,7 @@ __global__ void k_coarsen_faces(const double* __restrict__ fbx, const double* __
                 v = (fbz[fz_index(f, 2 * X, 2 * Y, 2 * Z)] + fbz[fz_index(f, 2 * X + 1, 2 * Y, 2 * Z)] +
                      fbz[fz_index(f, 2 * X, 2 * Y + 1, 2 * Z)] + fbz[fz_index(f, 2 * X + 1, 2 * Y + 1, 2 * Z)]) / 4.0;
             cbz[h] = v;
+            if (f32) sbz[h] = (float)v;
         }
     }
 }

@@ -34,7 +34,7 @@
 
 namespace mgp {
 
-template <int TX_, int TY>
+template <int TX_, int TY, int E = 4>
 struct Sweep2Geom {
     static constexpr int TX = TX_;             // tile width (cells): 64, or 32 for 32-wide grids
     static constexpr int EX = TX + 8;          // LDS plane: x0-4 .. x0+TX+3
@@ -42,14 +42,17 @@ struct Sweep2Geom {
     static constexpr int HX = EX / 2;          // pairs per row
     static constexpr int NP = HX * EY;         // pairs per plane = working threads
     static constexpr int NT = (NP + 63) / 64 * 64;
-    // LDS row stride and offset of a row's odd-x cells.  64-wide tiles: a wave
-    // spans rows of 36 pairs; with RS +- HO = 36 (mod 32), the next row's cells
-    // of one colour start in the bank after the previous row's last, and
+    // LDS row stride and offset of a row's odd-x cells.  64-wide FP32 tiles: a
+    // wave spans rows of 36 pairs; with RS +- HO = 36 (mod 32), the next row's
+    // cells of one colour start in the bank after the previous row's last, and
     // 2 RS = 8 (mod 64): fewer bank conflicts than the packed 72 / 36 layout
     // (measured: 0.864 against 0.879 ms per 512^3 launch).  32-wide tiles (rows
-    // of 20 pairs): the same rule, RS - HO = 20 + 4.
-    static constexpr int RS = TX == 64 ? 100 : 56;
-    static constexpr int HO = TX == 64 ? 64 : 32;
+    // of 20 pairs): the same rule, RS - HO = 20 + 4.  FP64 (E = 8, a value
+    // takes two banks): 16 lanes cover all 32 banks, and with 2 RS = 8
+    // (mod 32) the 8 banks a row's last four pairs take are followed by the
+    // next row's first.
+    static constexpr int RS = E == 8 ? 84 : (TX == 64 ? 100 : 56);
+    static constexpr int HO = E == 8 ? 36 : (TX == 64 ? 64 : 32);
     static_assert(RS >= HO + HX, "a row's odd-x cells must not reach the next row");
     static constexpr int PLANE = RS * EY;
     static constexpr int SLOTS = 7;         // planes s-5 .. s+1 of step s
@@ -66,17 +69,25 @@ struct Sweep2Geom {
 // y-interpolated values (six coarse loads) are formed once and kept while the z
 // march needs them (two planes at a time).
 //
+// FP64: the coefficients of seven planes would not fit the registers of 14
+// waves, so the FP64 instance takes 64 x 8 tiles (9 waves) and keeps the
+// y-face coefficients in LDS planes beside the iterate (written once per plane
+// from a load one step ahead, like the iterate; the upper face of a cell is the
+// lower face of the cell above it); the other coefficients stay in registers.
+//
 // Launch contract: nx even and >= TX, ny >= TY, every array below 2^31 bytes,
-// grid = ntx * nty * ceil(nz / zc) blocks of Sweep2Geom<TX, TY>::NT threads.
+// grid = ntx * nty * ceil(nz / zc) blocks of Sweep2Geom<TX, TY, sizeof(T)>::NT threads.
 template <typename T, int TX, int TY>
-__global__ void __launch_bounds__((Sweep2Geom<TX, TY>::NT))
+__global__ void __launch_bounds__((Sweep2Geom<TX, TY, sizeof(T)>::NT))
 k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
                const T* __restrict__ bb, const T* __restrict__ in, T* __restrict__ out, Dims d, T h2, int c0,
                int zero_in, int zc, int ntx, int nty, const T* __restrict__ ec, Dims cd)
 {
-    using G = Sweep2Geom<TX, TY>;
+    using G = Sweep2Geom<TX, TY, sizeof(T)>;
     using T2 = typename Vec2<T>::type;
+    constexpr bool BYL = sizeof(T) == 8;  // y-face coefficients in LDS planes
     __shared__ T slot[G::SLOTS * G::PLANE];
+    __shared__ T yslot[BYL ? G::SLOTS * G::PLANE : 1];
     const int nb = (int)gridDim.x, bid = (int)blockIdx.x;
     const int q8 = nb / 8, r8 = nb % 8, xcd = bid % 8;
     const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + bid / 8;
@@ -105,6 +116,9 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     const unsigned oin = inside ? (unsigned)(gy * d.nx + gx0) * sizeof(T) : kOutside;
     const unsigned oc = coef_row ? (unsigned)(gy * d.nx + gx0) * sizeof(T) : kOutside;
     const unsigned ofx = coef_row ? (unsigned)(gy * (d.nx + 2) + gx0) * sizeof(T) : kOutside;
+    // (LDS y-faces) the lower y-face of every row but the first: the last row's
+    // is the upper face of the row below it
+    const unsigned oby = (inside && pyi >= 1) ? (unsigned)(gy * d.nx + gx0) * sizeof(T) : kOutside;
     const int le = G::idx(2 * pxi, pyi), lo = G::idx(2 * pxi + 1, pyi);
 
     auto cpl = [&](int z) { return (unsigned)min(max(z, 0), d.nz - 1); };
@@ -162,6 +176,7 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     // LDS plane of z-step position K (0..6) and plane offset dz from the step's
     // plane s: the loop is unrolled seven times, so slot numbers are constants
     auto plane = [&](int K, int dz) -> T* { return slot + ((K + dz + 7 * 7) % 7) * G::PLANE; };
+    auto yplane = [&](int K, int dz) -> T* { return yslot + ((K + dz + 7 * 7) % 7) * G::PLANE; };
     auto store_in = [&](T* P, T2 v) {
         if (active) {
             P[le] = v.x;
@@ -171,8 +186,11 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     // coefficients of the pair in one plane: lower z-faces (loaded first: the
     // stage one plane down needs them as its upper faces one step earlier than
     // the rest), rhs, x-faces (3), y-faces below and above
-    struct Coef {
-        T2 bz, b, bx, by, byu;
+    struct CoefY {
+        T2 by, byu;
+    };
+    struct Coef : std::conditional_t<BYL, Vec2<T>, CoefY> {
+        T2 bz, b, bx;
         T bxn;
     };
     auto load_coef = [&](int z, Coef& C) {
@@ -182,9 +200,12 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         C.b = bload2<T>(r_b, oc, zz * psz);
         C.bx = bload2<T>(r_bx, ofx, zz * pfx);
         C.bxn = bload1<T>(r_bx, ofx, zz * pfx + 2u * sizeof(T));
-        C.by = bload2<T>(r_by, oc, zz * pfy);
-        C.byu = bload2<T>(r_by, oc, zz * pfy + rowb);
+        if constexpr (!BYL) {
+            C.by = bload2<T>(r_by, oc, zz * pfy);
+            C.byu = bload2<T>(r_by, oc, zz * pfy + rowb);
+        }
     };
+    auto load_y = [&](int z) -> T2 { return bload2<T>(r_by, oby, cpl(z) * pfy); };
 
     // Which cell of the pair a stage relaxes, and whether it lies in the
     // stage's ring: bit 2r + o of `ring` says cell o (0 even x, 1 odd x) of
@@ -202,8 +223,8 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     // Half-sweep of the colour-`col` cell of the pair on plane z (LDS planes
     // Pm, P0, Pp hold z-1, z, z+1), if that cell lies in the tile + r ring and
     // in the domain; the value goes to `v`, its LDS index to `li`.
-    auto relax = [&](int z, int col, int r, const T* Pm, const T* P0, const T* Pp, const Coef& C, const Coef& Cup,
-                     bool& ok, int& li, T& v) {
+    auto relax = [&](int z, int col, int r, const T* Pm, const T* P0, const T* Pp, const T* Y0, const Coef& C,
+                     const Coef& Cup, bool& ok, int& li, T& v) {
         const int odd = gyp ^ ((z + col) & 1);
         ok = z >= 0 && z < d.nz && ((ring >> (2 * r + odd)) & 1);
         li = odd ? lo : le;
@@ -212,8 +233,14 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         const int xm = odd ? le : lo - 1;
         const T bxl = odd ? C.bx.y : C.bx.x;
         const T bxh = odd ? C.bxn : C.bx.y;
-        const T byl = odd ? C.by.y : C.by.x;
-        const T byh = odd ? C.byu.y : C.byu.x;
+        T byl, byh;
+        if constexpr (BYL) {
+            byl = Y0[li];
+            byh = Y0[li + G::RS];
+        } else {
+            byl = odd ? C.by.y : C.by.x;
+            byh = odd ? C.byu.y : C.byu.x;
+        }
         const T bzl = odd ? C.bz.y : C.bz.x;
         const T bzh = odd ? Cup.bz.y : Cup.bz.x;
         const T b = odd ? C.b.y : C.b.x;
@@ -239,12 +266,14 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     // stage needs any more, so the seven sets rotate by name.  A stage on plane
     // z takes its upper z-faces from the set of plane z+1.  The iterate of
     // plane s+2 is loaded first in the step and written to LDS at the next step.
-    T2 v;
+    T2 v, yv;
     auto step = [&](auto Kc, int s, Coef& Ln, const Coef& Cp1, const Coef& Cs, const Coef& Cm1, const Coef& Cm2,
                     const Coef& Cm3, const Coef& Cm4) {
         constexpr int K = decltype(Kc)::value;
         store_in(plane(K, 1), v);
+        if constexpr (BYL) store_in(yplane(K, 1), yv);
         v = load_in(s + 2);
+        if constexpr (BYL) yv = load_y(s + 2);
         load_coef(s + 2, Ln);
         lds_barrier();
         // phase 1: A1 on plane s and A2 on plane s-3 (disjoint planes and states)
@@ -252,14 +281,14 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
             bool ok;
             int li;
             T a = (T)0;
-            relax(s, cA, 3, plane(K, -1), plane(K, 0), plane(K, 1), Cs, Cp1, ok, li, a);
+            relax(s, cA, 3, plane(K, -1), plane(K, 0), plane(K, 1), yplane(K, 0), Cs, Cp1, ok, li, a);
             if (ok) plane(K, 0)[li] = a;
         }
         if (s - 3 >= z0 - 1 && s - 3 <= z1) {
             bool ok;
             int li;
             T a = (T)0;
-            relax(s - 3, cA, 1, plane(K, -4), plane(K, -3), plane(K, -2), Cm3, Cm2, ok, li, a);
+            relax(s - 3, cA, 1, plane(K, -4), plane(K, -3), plane(K, -2), yplane(K, -3), Cm3, Cm2, ok, li, a);
             if (ok) plane(K, -3)[li] = a;
         }
         lds_barrier();
@@ -268,7 +297,7 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
             bool ok;
             int li;
             T bv = (T)0;
-            relax(s - 1, cB, 2, plane(K, -2), plane(K, -1), plane(K, 0), Cm1, Cs, ok, li, bv);
+            relax(s - 1, cB, 2, plane(K, -2), plane(K, -1), plane(K, 0), yplane(K, -1), Cm1, Cs, ok, li, bv);
             if (ok) plane(K, -1)[li] = bv;
         }
         const int zb = s - 4;
@@ -276,7 +305,7 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
             bool ok;
             int li;
             T bv = (T)0;
-            relax(zb, cB, 0, plane(K, -5), plane(K, -4), plane(K, -3), Cm4, Cm3, ok, li, bv);
+            relax(zb, cB, 0, plane(K, -5), plane(K, -4), plane(K, -3), yplane(K, -4), Cm4, Cm3, ok, li, bv);
             const bool bodd = li == lo;
             const T av = plane(K, -4)[bodd ? le : lo];
             T2 o;
@@ -289,6 +318,10 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     store_in(plane(0, -1), load_in(sbeg - 1));
     store_in(plane(0, 0), load_in(sbeg));
     v = load_in(sbeg + 1);
+    if constexpr (BYL) {
+        store_in(yplane(0, 0), load_y(sbeg));
+        yv = load_y(sbeg + 1);
+    }
     Coef R0, R1, R2, R3, R4, R5, R6;
     load_coef(sbeg, R0);
     load_coef(sbeg + 1, R1);
@@ -344,12 +377,19 @@ inline Sweep2Launch sweep2_geom(const Dims& d)
     return g;
 }
 
-// Grids the two-sweep kernel serves: at least 32 cells wide (even; 64-wide
-// tiles from 64 cells on) and 16 rows, arrays below 2^31 bytes.
+// Tile rows of the two-sweep launches: 16 in FP32, 8 in FP64.
+template <typename T>
+constexpr int sweep2_ty() { return sizeof(T) == 8 ? 8 : 16; }
+
+// Grids the two-sweep kernel serves: FP32 at least 32 cells wide (even; 64-wide
+// tiles from 64 cells on) and 16 rows; FP64 at least 64 cells wide (even) and
+// 8 rows; arrays below 2^31 bytes.
 inline bool sweep2_ok(const Dims& d, size_t elem)
 {
     const long big = n_fx(d) > n_fz(d) ? n_fx(d) : n_fz(d);
-    return elem == 4 && d.nx >= 32 && (d.nx % 2) == 0 && d.ny >= 16 && big * (long)elem < (1L << 31);
+    if (big * (long)elem >= (1L << 31) || (d.nx % 2) != 0) return false;
+    if (elem == 4) return d.nx >= 32 && d.ny >= 16;
+    return elem == 8 && d.nx >= 64 && d.ny >= 8;
 }
 
 // the launches with 64-wide tiles (the timed ones)
@@ -363,17 +403,19 @@ hipError_t launch_sweep2(const T* bx, const T* by, const T* bz, Dims d, T h2, co
                          int order, bool zero_in, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                          const T* ec = nullptr)
 {
-    constexpr int TY = 16;
+    constexpr int TY = sweep2_ty<T>();
     const Dims cd{d.nx / 2, d.ny / 2, d.nz / 2};
     const int c0 = order == 0 ? 0 : 1, zi = zero_in ? 1 : 0;
     if (sweep2_wide(d)) {
         const Sweep2Launch g = sweep2_geom<64, TY>(d);
-        hipExtLaunchKernelGGL(k_sweep2_fused<T, 64, TY>, dim3(g.blocks), dim3(Sweep2Geom<64, TY>::NT), 0, s, ev0, ev1,
-                              0, bx, by, bz, b, in, out, d, h2, c0, zi, g.zc, g.ntx, g.nty, ec, cd);
-    } else {
+        hipExtLaunchKernelGGL(k_sweep2_fused<T, 64, TY>, dim3(g.blocks), dim3(Sweep2Geom<64, TY, sizeof(T)>::NT), 0, s,
+                              ev0, ev1, 0, bx, by, bz, b, in, out, d, h2, c0, zi, g.zc, g.ntx, g.nty, ec, cd);
+    } else if constexpr (sizeof(T) == 4) {
         const Sweep2Launch g = sweep2_geom<32, TY>(d);
         hipExtLaunchKernelGGL(k_sweep2_fused<T, 32, TY>, dim3(g.blocks), dim3(Sweep2Geom<32, TY>::NT), 0, s, ev0, ev1,
                               0, bx, by, bz, b, in, out, d, h2, c0, zi, g.zc, g.ntx, g.nty, ec, cd);
+    } else {
+        return hipErrorInvalidValue;  // FP64 pairs only on 64-wide grids (sweep2_ok)
     }
     return hipGetLastError();
 }

@@ -141,10 +141,11 @@ def test_kernel_timing_stats(density):
             expect = {L.MG_K_SWEEP2R: n, L.MG_K_SWEEP2: n, L.MG_K_RESTRICT: 0, L.MG_K_PROLONG: 0,
                       L.MG_K_OUTER: n}
         else:
-            # the first cycle runs both pre-sweeps; every later one starts with the
-            # sweep that also takes the norm of the previous result, and so does the
-            # final check
-            expect = {L.MG_K_SWEEP: 3 * n + 1, L.MG_K_NORM: n, L.MG_K_RESTRICT: n, L.MG_K_PROLONG: n}
+            # pre- and post-smoothing each one two-sweep launch (the post-smoothing
+            # one prolongates the coarse correction itself); the norm of each
+            # cycle's result is a residual pass of its own
+            expect = {L.MG_K_SWEEP2: 2 * n, L.MG_K_SWEEP: 0, L.MG_K_NORM: n, L.MG_K_RESTRICT: n,
+                      L.MG_K_PROLONG: 0}
         # (mixed) the next cycle's pre-sweeps are queued while the host waits for a
         # norm; one such launch may run in vain after the last cycle
         spare = 1 if precision == "mixed" and st.kernel_launches[L.MG_K_SWEEP2R] == n + 1 else 0

@@ -62,26 +62,31 @@ def kernel_symbol(name, precision, coefficients):
     return sym.format(rho="true" if coefficients == "density" else "false") if sym else None
 
 # HBM bytes per dispatch of the FP32 two-sweep smoother on the 512^3 film + 32
-# drops workload (average over all levels, the unit of the roofline figure), from
-# two rocprofv3 PMC passes over one step: FETCH_SIZE and WRITE_SIZE in KiB, scaled
-# by what the same counters read for a plain 1 GiB device copy (x2.0 and x1.0 on
-# this part).  Valid only for the sources they were taken on (the kernel and the
-# host code that decides its launches): the hash below is recomputed at run time
-# and the figure is dropped (null) once the sources differ.
+# drops workload, from two rocprofv3 PMC passes over one benchmark step
+# (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch), scaled by what the same
+# counters read for a plain 1 GiB device copy (x2.0 and x1.0 on this part):
+# averaged over all its dispatches (every level, the unit of the roofline
+# figure) and over the finest grid's alone.  Valid only for the sources they
+# were taken on (the kernel and the host code that decides its launches): the
+# hash below is recomputed at run time and the figure is dropped (null) once
+# the sources differ.
 TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 64, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "35aa7411dc1cf334c4ef0f88e3f3e983de78b6aeea665df58766226076b295cf",
-    "fetch_kib": 379839.44235777244,
-    "write_kib": 149760.02196013622,
+    "sha256": "18f51d778298412b5e2b5098963dc3b57ecb07de7a36895bd35936444375d4c0",
+    "fetch_kib": 428402.7944711539,
+    "write_kib": 149760.00100160256,
+    "finest_fetch_kib": 1472576.8325320513,
+    "finest_write_kib": 524288.0040064103,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
 
 
-def measured_traffic(kernel: str, n: int):
-    """Scaled HBM bytes per dispatch for `kernel`, or None when no counters match it."""
+def measured_traffic(kernel: str, n: int, finest: bool = False):
+    """Scaled HBM bytes per dispatch for `kernel` (all dispatches, or the finest
+    grid's), or None when no counters match it."""
     import hashlib
     if kernel != TRAFFIC["kernel"] or n != TRAFFIC["n"]:
         return None
@@ -91,7 +96,9 @@ def measured_traffic(kernel: str, n: int):
             h.update(f.read())
     if h.hexdigest() != TRAFFIC["sha256"]:
         return None
-    return (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]) * 1024.0
+    pre = "finest_" if finest else ""
+    return (TRAFFIC[pre + "fetch_kib"] * TRAFFIC["fetch_scale"] +
+            TRAFFIC[pre + "write_kib"] * TRAFFIC["write_scale"]) * 1024.0
 
 
 def log(msg: str) -> None:
@@ -505,6 +512,11 @@ def main() -> int:
                                    "bandwidth; one pass over memory does two sweeps)")
         roofline["traffic_gbps"] = tr / (d["avg_ms"] * 1e-3) / 1e9 if tr else None
         roofline["traffic_frac"] = roofline["traffic_gbps"] / HBM_PEAK_GBPS if tr else None
+        trf = measured_traffic(d["kernel"], n, finest=True)
+        fin = roofline["finest"]
+        fin["traffic"] = trf
+        fin["traffic_gbps"] = trf / (fin["avg_ms"] * 1e-3) / 1e9 if (trf and fin.get("avg_ms")) else None
+        fin["traffic_frac"] = fin["traffic_gbps"] / HBM_PEAK_GBPS if fin["traffic_gbps"] else None
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -85,7 +85,14 @@ k_faces_march(Op op, Dims d, int rx, int zc, int ntx, int nty, long ntiles, doub
     const bool f32 = fx != nullptr;
     const long sy = d.nx, sz = (long)d.nx * d.ny;
     double bad = 0.0;
-    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // XCD-aware order: the hardware deals blocks round-robin to the 8 XCDs, so
+    // consecutive block ids are remapped to consecutive tiles of one XCD; a
+    // tile's left neighbour (whose cache line its first column's x-1 read
+    // touches) and the row of tiles below then share its L2
+    const int nb = (int)gridDim.x, bid = (int)blockIdx.x;
+    const int q8 = nb / 8, r8 = nb % 8, xcd = bid % 8;
+    const long logical = (long)xcd * q8 + (xcd < r8 ? xcd : r8) + bid / 8;
+    for (long tile = logical; tile < ntiles; tile += nb) {
         const int tx = (int)(tile % ntx);
         const long rest = tile / ntx;
         const int ty = (int)(rest % nty);

@@ -33,6 +33,18 @@
 
 namespace mgp {
 
+// Vector stores through a buffer resource (32-bit lane offset, plane offset in
+// an SGPR): no 64-bit per-lane address is kept live for the output arrays.
+__device__ __forceinline__ void bstore1f(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore2f(__amdgpu_buffer_rsrc_t r, float2 v, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, voff,
+                                          soff, 0);
+}
+
 // Launch contract: nx even and >= 64, ny even and >= TY, nz even, zc even,
 // every array below 2^31 bytes, grid = ntx * nty * ceil(nz / zc) blocks of
 // Sweep2Geom<64, TY>::NT threads; coarse has the (nx/2, ny/2, nz/2) layout.
@@ -73,6 +85,12 @@ k_sweep2_restrict(const float* __restrict__ bx, const float* __restrict__ by, co
     const auto r_by = make_rsrc(by, (unsigned)(n_fy(d) * sizeof(T)));
     const auto r_bz = make_rsrc(bz, (unsigned)(n_fz(d) * sizeof(T)));
     const unsigned oc = inside ? (unsigned)(gy * d.nx + gx0) * sizeof(T) : kOutside;
+    const auto r_out = make_rsrc(out, (unsigned)(ncell * sizeof(T)));
+    const long ccell = (long)(d.nx / 2) * (d.ny / 2) * (d.nz / 2);
+    const auto r_coarse = make_rsrc(coarse, (unsigned)(ccell * sizeof(T)));
+    // lane offset of the pair's coarse cell within a coarse plane (even rows write)
+    const unsigned occ = (unsigned)(((gy >> 1) * (d.nx / 2) + (gx0 >> 1)) * sizeof(T));
+    const unsigned cpsz = (unsigned)((long)(d.nx / 2) * (d.ny / 2) * sizeof(T));
     const unsigned ofx = inside ? (unsigned)(gy * (d.nx + 2) + gx0) * sizeof(T) : kOutside;
     const int le = G::idx(2 * pxi, pyi), lo = G::idx(2 * pxi + 1, pyi);
 
@@ -151,7 +169,6 @@ k_sweep2_restrict(const float* __restrict__ bx, const float* __restrict__ by, co
 
     const int cA = c0, cB = 1 - c0;
     const int sbeg = z0 - 4, send = z1 + 5;
-    const int cnx = d.nx / 2, cny = d.ny / 2;
     T rB_prev = (T)0, p_own = (T)0, racc = (T)0;
     // the A-cell's coefficients of plane s-5, taken out of its set before the set
     // is reloaded (the upper z-face comes from the set of plane s-4)
@@ -172,7 +189,7 @@ k_sweep2_restrict(const float* __restrict__ bx, const float* __restrict__ by, co
             if (core && !odd_row && zr >= z0 && zr < z1) {
                 racc += p_own + rbuf[rb];
                 if (zr & 1) {
-                    coarse[((long)(zr >> 1) * cny + (gy >> 1)) * cnx + (gx0 >> 1)] = racc * (T)0.125;
+                    bstore1f(r_coarse, racc * (T)0.125, occ, (unsigned)(zr >> 1) * cpsz);
                     racc = (T)0;
                 }
             }
@@ -223,7 +240,7 @@ k_sweep2_restrict(const float* __restrict__ bx, const float* __restrict__ by, co
                 T2 o;
                 o.x = bodd ? av : bv;
                 o.y = bodd ? bv : av;
-                *reinterpret_cast<T2*>(out + (long)zb * d.nx * d.ny + (long)gy * d.nx + gx0) = o;
+                bstore2f(r_out, o, oc, (unsigned)zb * psz);
             }
         }
         // A-cell of plane s-5 (planes s-6, s-5 are final and untouched in this

@@ -75,10 +75,10 @@ TRAFFIC = {
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
     "sha256": "18f51d778298412b5e2b5098963dc3b57ecb07de7a36895bd35936444375d4c0",
-    "fetch_kib": 428402.7944711539,
-    "write_kib": 149760.00100160256,
-    "finest_fetch_kib": 1472576.8325320513,
-    "finest_write_kib": 524288.0040064103,
+    "fetch_kib": 428496.9,
+    "write_kib": 149760.0,
+    "finest_fetch_kib": 1472854.1,
+    "finest_write_kib": 524288.0,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

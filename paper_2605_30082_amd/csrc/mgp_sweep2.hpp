@@ -48,11 +48,13 @@ struct Sweep2Geom {
     // 2 RS = 8 (mod 64): fewer bank conflicts than the packed 72 / 36 layout
     // (measured: 0.864 against 0.879 ms per 512^3 launch).  32-wide tiles (rows
     // of 20 pairs): the same rule, RS - HO = 20 + 4.  FP64 (E = 8, a value
-    // takes two banks): 16 lanes cover all 32 banks, and with 2 RS = 8
-    // (mod 32) the 8 banks a row's last four pairs take are followed by the
-    // next row's first.
+    // takes two banks, 16 lanes cover the 32 banks): consecutive rows of a
+    // wave read opposite halves (a stage relaxes the even cells of one row and
+    // the odd cells of the next), so a group of 16 lanes that holds the last k
+    // pairs of one row and the first 16 - k of the next is free of conflicts
+    // when RS + HO = RS - HO = 4 (mod 16): RS = 84, HO = 48.
     static constexpr int RS = E == 8 ? 84 : (TX == 64 ? 100 : 56);
-    static constexpr int HO = E == 8 ? 36 : (TX == 64 ? 64 : 32);
+    static constexpr int HO = E == 8 ? 48 : (TX == 64 ? 64 : 32);
     static_assert(RS >= HO + HX, "a row's odd-x cells must not reach the next row");
     static constexpr int PLANE = RS * EY;
     static constexpr int SLOTS = 7;         // planes s-5 .. s+1 of step s

@@ -114,6 +114,16 @@ def test_single_kernels_512(big, precision):
     got = N(s.residual_restrict(gd, T(p), level=0, precision=precision))
     ref = oracle.restrict(oracle.residual(ob, od, p, wl.h))
     assert max_rel(got, ref) < tol * 10
+    # the V-cycle's pre-smoothing from zero and the restriction of its residual
+    # (FP32: one launch of the fused kernel, as the benchmark's V-cycles run it)
+    pz, bc = s.presmooth_restrict(gd, level=0, precision=precision)
+    pz = N(pz)
+    ref = np.zeros_like(p)
+    for c in (0, 1, 0, 1):
+        ref = oracle.rbgs_half(ob, od, ref, wl.h, c)
+    assert max_rel(pz, ref) < tol, ("presmooth", max_rel(pz, ref))
+    ref = oracle.restrict(oracle.residual(ob, od, pz, wl.h))
+    assert max_rel(N(bc), ref) < tol * 10, ("restrict", max_rel(N(bc), ref))
     e = g.standard_normal((256, 256, 256))
     got = N(s.prolong_correct(T(e), T(p), level=0, precision=precision))
     assert max_rel(got, oracle.prolong_add(e, p)) < tol

@@ -74,10 +74,10 @@ TRAFFIC = {
     "kernel": "mgp::k_sweep2_fused<float, 64, 16>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "18f51d778298412b5e2b5098963dc3b57ecb07de7a36895bd35936444375d4c0",
-    "fetch_kib": 428496.9,
+    "sha256": "cc56c59e95dc051389d669f350231b9472111ede6bb3fafd24871ac07b7beb0e",
+    "fetch_kib": 428362.8,
     "write_kib": 149760.0,
-    "finest_fetch_kib": 1472854.1,
+    "finest_fetch_kib": 1472307.3,
     "finest_write_kib": 524288.0,
     "fetch_scale": 2.0,
     "write_scale": 1.0,

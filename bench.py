@@ -43,8 +43,8 @@ SWEEPS_PER_LAUNCH = {"sweep": 1, "sweep2": 2, "sweep2_restrict": 2}
 KERNEL_SYMBOLS = {
     ("sweep", "mixed"): "mgp::k_sweep_fused<float, 8, false>",
     ("sweep", "fp64"): "mgp::k_sweep_fused<double, 16, false>",
-    ("sweep2", "fp64"): "mgp::k_sweep2_fused<double, 64, 8>",
-    ("sweep2", "mixed"): "mgp::k_sweep2_fused<float, 64, 16>",
+    ("sweep2", "fp64"): "mgp::k_sweep2_fused<double, 64, 8, {pro}>",
+    ("sweep2", "mixed"): "mgp::k_sweep2_fused<float, 64, 16, true>",
     ("sweep2_restrict", "mixed"): "mgp::k_sweep2_restrict<16>",
     ("residual_restrict", "mixed"): "mgp::k_resid<float, 1, false>",
     ("residual_restrict", "fp64"): "mgp::k_resid<double, 1, {rho}>",
@@ -57,9 +57,15 @@ KERNEL_SYMBOLS = {
 
 def kernel_symbol(name, precision, coefficients):
     """rocprofv3's name of the kernel timed for a class; finest-grid FP64 residual
-    passes have a density-fed instance (coefficients formed from rho)."""
+    passes have a density-fed instance (coefficients formed from rho).  The FP64
+    two-sweep class runs two instances: pre-smoothing, and post-smoothing that
+    takes the coarse correction with it (the FP32 pre-smoothing is its own class)."""
     sym = KERNEL_SYMBOLS.get((name, precision))
-    return sym.format(rho="true" if coefficients == "density" else "false") if sym else None
+    if sym is None:
+        return None
+    if "{pro}" in sym:
+        return sym.format(pro="false") + " (pre-smoothing); " + sym.format(pro="true") + " (post-smoothing)"
+    return sym.format(rho="true" if coefficients == "density" else "false")
 
 # HBM bytes per dispatch of the FP32 two-sweep smoother on the 512^3 film + 32
 # drops workload, from two rocprofv3 PMC passes over one benchmark step
@@ -71,7 +77,7 @@ def kernel_symbol(name, precision, coefficients):
 # hash below is recomputed at run time and the figure is dropped (null) once
 # the sources differ.
 TRAFFIC = {
-    "kernel": "mgp::k_sweep2_fused<float, 64, 16>",
+    "kernel": "mgp::k_sweep2_fused<float, 64, 16, true>",
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
     "sha256": "cc56c59e95dc051389d669f350231b9472111ede6bb3fafd24871ac07b7beb0e",
@@ -152,7 +158,7 @@ def kernel_summary(stats_list, precision, coefficients):
                          "finest": {"launches": n0, "avg_ms": ms0 / n0 if n0 else None,
                                     "alg_bytes_per_launch": by0 / n0 if n0 else None,
                                     "achieved_gbps": by0 / (ms0 * 1e-3) / 1e9 if ms0 > 0 else None}}
-            if sym and sym.endswith("true>") and n > n0:
+            if "{rho}" in KERNEL_SYMBOLS.get((name, precision), "") and coefficients == "density" and n > n0:
                 # the density-fed instance runs on the finest grid only; coarser grids use the face arrays
                 out[name]["kernel"] = sym + " (finest grid); " + sym.replace("true>", "false>") + " (coarser grids)"
     return out
@@ -257,11 +263,11 @@ def copy_calibration() -> int:
 def probe_smoothers(args) -> int:
     """The finest-grid smoothers alone, through the single-kernel entry points
     mg_smooth and mg_presmooth_restrict, on the workload's density field: three
-    FP32 two-sweep launches (k_sweep2_fused<float, 64, 16>, from a non-zero
+    FP32 two-sweep launches (k_sweep2_fused<float, 64, 16, false>, from a non-zero
     iterate), three FP32 pre-smoothing launches from zero that also restrict the
     residual (k_sweep2_restrict<16>), three FP64 one-sweep launches
     (k_sweep_fused<double, 16, false>) and three FP64 two-sweep launches
-    (k_sweep2_fused<double, 64, 8>).  The entry points also cast their FP64
+    (k_sweep2_fused<double, 64, 8, false>).  The entry points also cast their FP64
     arguments to the context's FP32 copies and back (k_convert launches).
     Prints one JSON line of HIP-event times around each call."""
     import numpy as np

@@ -64,12 +64,17 @@ struct Sweep2Geom {
 };
 
 // Post-smoothing right after a coarse-grid correction can take the correction
-// with it (ec != NULL, coarse dims cd = d / 2): the iterate is then read as
+// with it (PRO, coarse dims cd = d / 2): the iterate is then read as
 // in + P ec, P the trilinear prolongation, so the separate prolongation pass
 // (read in, write in) goes away.  The value is the one k_prolong_tiled writes:
-// pro_lerp along x, then y, then z.  Per pair and coarse plane the x- and
-// y-interpolated values (six coarse loads) are formed once and kept while the z
-// march needs them (two planes at a time).
+// pro_lerp along x, then y, then z.  Fine plane z lies between coarse planes
+// (z - 1) / 2 and (z + 1) / 2 (clamped), so the z march needs a window of two
+// coarse planes that moves up by one plane every second fine plane.  Per pair
+// the window holds the x- and y-interpolated values of its two planes; the six
+// coarse loads of the plane that enters next are issued when the window moves,
+// two steps before they are interpolated, and the correction is added when the
+// fine plane goes to LDS, a step after its load: no load is waited for in the
+// step that issues it.
 //
 // FP64: the coefficients of seven planes would not fit the registers of 14
 // waves, so the FP64 instance takes 64 x 8 tiles (9 waves) and keeps the
@@ -78,8 +83,9 @@ struct Sweep2Geom {
 // lower face of the cell above it); the other coefficients stay in registers.
 //
 // Launch contract: nx even and >= TX, ny >= TY, every array below 2^31 bytes,
-// grid = ntx * nty * ceil(nz / zc) blocks of Sweep2Geom<TX, TY, sizeof(T)>::NT threads.
-template <typename T, int TX, int TY>
+// grid = ntx * nty * ceil(nz / zc) blocks of Sweep2Geom<TX, TY, sizeof(T)>::NT
+// threads; PRO: nx, ny, nz even, ec the d / 2 grid, zero_in 0.
+template <typename T, int TX, int TY, bool PRO>
 __global__ void __launch_bounds__((Sweep2Geom<TX, TY, sizeof(T)>::NT))
 k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
                const T* __restrict__ bb, const T* __restrict__ in, T* __restrict__ out, Dims d, T h2, int c0,
@@ -124,56 +130,98 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     const int le = G::idx(2 * pxi, pyi), lo = G::idx(2 * pxi + 1, pyi);
 
     auto cpl = [&](int z) { return (unsigned)min(max(z, 0), d.nz - 1); };
-    const bool pro = ec != nullptr;
-    const auto r_e = make_rsrc(ec, pro ? (unsigned)((long)cd.nx * cd.ny * cd.nz * sizeof(T)) : 0u);
+    const auto r_e = make_rsrc(ec, PRO ? (unsigned)((long)cd.nx * cd.ny * cd.nz * sizeof(T)) : 0u);
     const unsigned cpb = (unsigned)((long)cd.nx * cd.ny * sizeof(T));
-    // x- and y-interpolated correction of coarse plane K for the pair's two cells
-    auto coarse_xy = [&](int K) -> T2 {
-        const int I = gx0 >> 1, J = gy >> 1;
-        const int Im = max(I - 1, 0), Ip = min(I + 1, cd.nx - 1);
-        const int Jn = (gy & 1) ? min(J + 1, cd.ny - 1) : max(J - 1, 0);
-        const unsigned r0 = (unsigned)(J * cd.nx), r1 = (unsigned)(Jn * cd.nx);
-        const unsigned so = (unsigned)K * cpb;
-        auto ld = [&](unsigned row, int i) {
-            return bload1<T>(r_e, inside ? (row + (unsigned)i) * (unsigned)sizeof(T) : kOutside, so);
-        };
-        const T m0 = ld(r0, I), m1 = ld(r1, I);
-        const T a0 = pro_lerp(m0, ld(r0, Im)), a1 = pro_lerp(m0, ld(r0, Ip));
-        const T b0 = pro_lerp(m1, ld(r1, Im)), b1 = pro_lerp(m1, ld(r1, Ip));
+    // A coarse plane goes through LDS as the block's patch of it: columns
+    // x0/2 - 3 .. x0/2 + TX/2 + 2 and rows y0/2 - 3 .. y0/2 + TY/2 + 2, each
+    // coordinate clamped to the grid (so the patch holds the clamped
+    // neighbours the prolongation takes at the walls), one value per thread.
+    // Fine plane z lies between coarse planes hu(z) - 1 and hu(z) (clamped),
+    // hu(z) = floor((z + 1) / 2), which moves up at odd z; plane c lives in
+    // LDS slot c mod 3 from before its first use to after its last.
+    constexpr int CPX = TX / 2 + 6, CPY = TY / 2 + 6, CPN = CPX * CPY;
+    static_assert(CPN <= G::NT, "one patch value per thread");
+    __shared__ T cslot[PRO ? 3 * CPN : 1];
+    const unsigned ocp = [&] {
+        if (t >= CPN) return kOutside;
+        const int ci = min(max(x0 / 2 - 3 + t % CPX, 0), cd.nx - 1);
+        const int cj = min(max(y0 / 2 - 3 + t / CPX, 0), cd.ny - 1);
+        return (unsigned)(cj * cd.nx + ci) * (unsigned)sizeof(T);
+    }();
+    auto hu_of = [](int z) { return (z + 1) >> 1; };
+    auto cbase = [&](int c) { return cslot + ((c + 3) % 3) * CPN; };  // c >= -3
+    // (the plane offset is wave-uniform; said so, or the compiler loops over lanes)
+    auto patch_load = [&](int c) {
+        const unsigned so = (unsigned)__builtin_amdgcn_readfirstlane(min(max(c, 0), cd.nz - 1)) * cpb;
+        return bload1<T>(r_e, ocp, so);
+    };
+    auto patch_store = [&](int c, T q) {
+        if (t < CPN) cbase(c)[t] = q;
+    };
+    // patch positions of the pair's coarse cell (I, J) and of (I, Jn), Jn the
+    // coarse row on the pair's side; I - 1 and I + 1 lie beside them
+    const int pm0 = ((gy >> 1) - (y0 / 2 - 3)) * CPX + ((gx0 >> 1) - (x0 / 2 - 3));
+    const int pm1 = pm0 + ((gy & 1) ? CPX : -CPX);
+    // x- and y-interpolated correction of coarse plane c for the pair's two cells
+    auto coarse_xy = [&](int c) -> T2 {
+        const T* C = cbase(c);
+        const T m0 = C[pm0], m1 = C[pm1];
+        const T a0 = pro_lerp(m0, C[pm0 - 1]), a1 = pro_lerp(m0, C[pm0 + 1]);
+        const T b0 = pro_lerp(m1, C[pm1 - 1]), b1 = pro_lerp(m1, C[pm1 + 1]);
         T2 p;
         p.x = pro_lerp(a0, b0);
         p.y = pro_lerp(a1, b1);
         return p;
     };
-    // the two coarse planes in hand; a miss replaces the lower one (z only grows)
-    T2 Pa, Pb;
-    Pa.x = Pa.y = Pb.x = Pb.y = (T)0;
-    int Ka = -1, Kb = -1;
-    auto fetch = [&](int K) -> T2 {
-        if (K == Ka) return Pa;
-        if (K == Kb) return Pb;
-        const T2 p = coarse_xy(K);
-        if (Ka < Kb) {
-            Pa = p;
-            Ka = K;
-        } else {
-            Pb = p;
-            Kb = K;
+    // The step that stores fine plane z to LDS stores the patch of plane
+    // hu(z + 1) when it is a new one (z even), loaded a step earlier, and loads
+    // that of hu(z + 2): every step loads (half of the loads repeat a plane),
+    // so no load result passes through a conditional assignment, which would
+    // make the compiler wait for it, and with it for every load in flight, in
+    // the step that issues it.
+    T Qn;
+    auto patch_step = [&](int z) {
+        if (!(z & 1)) patch_store(hu_of(z + 1), Qn);
+        Qn = patch_load(hu_of(z + 2));
+    };
+    // FP32 keeps the interpolated values of planes hu(z) - 1 and hu(z) of the
+    // plane z last stored in registers (W0, W1; a step reads one plane from
+    // LDS); FP64 has no registers to spare for them and reads both planes at
+    // each use.
+    constexpr bool WIN = sizeof(T) == 4;
+    T2 W0, W1;
+    auto move_window = [&](int z) {
+        const T2 n = coarse_xy(hu_of(z));
+        const bool up = (z & 1) != 0;
+        W0.x = up ? W1.x : W0.x;
+        W0.y = up ? W1.y : W0.y;
+        W1 = n;
+    };
+    // the iterate of fine plane z with the correction added: fine plane 2K
+    // takes coarse planes K and K-1, plane 2K+1 K and K+1 (clamped)
+    auto corrected = [&](int z, T2 v) -> T2 {
+        if constexpr (PRO) {
+            if constexpr (WIN) move_window(z);
+            if (inside && z >= 0 && z < d.nz) {
+                T2 hi, lo;
+                if constexpr (WIN) {
+                    hi = W1;
+                    lo = W0;
+                } else {
+                    hi = coarse_xy(hu_of(z));
+                    lo = coarse_xy(hu_of(z) - 1);
+                }
+                const bool odd = (z & 1) != 0;
+                const T2 n = odd ? lo : hi, f = odd ? hi : lo;
+                v.x = v.x + pro_lerp(n.x, f.x);
+                v.y = v.y + pro_lerp(n.y, f.y);
+            }
         }
-        return p;
+        return v;
     };
     auto load_in = [&](int z) -> T2 {
         const bool zv = !zero_in && z >= 0 && z < d.nz;
-        T2 v = bload2<T>(zv ? r_in : r_null, oin, cpl(z) * psz);
-        if (pro && zv) {
-            // fine plane 2K takes coarse planes K and K-1, plane 2K+1 K and K+1 (clamped)
-            const int K = z >> 1;
-            const int Kn = (z & 1) ? min(K + 1, cd.nz - 1) : max(K - 1, 0);
-            const T2 p = fetch(K), q = fetch(Kn);
-            v.x = v.x + pro_lerp(p.x, q.x);
-            v.y = v.y + pro_lerp(p.y, q.y);
-        }
-        return v;
+        return bload2<T>(zv ? r_in : r_null, oin, cpl(z) * psz);
     };
     // LDS plane of z-step position K (0..6) and plane offset dz from the step's
     // plane s: the loop is unrolled seven times, so slot numbers are constants
@@ -272,7 +320,8 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     auto step = [&](auto Kc, int s, Coef& Ln, const Coef& Cp1, const Coef& Cs, const Coef& Cm1, const Coef& Cm2,
                     const Coef& Cm3, const Coef& Cm4) {
         constexpr int K = decltype(Kc)::value;
-        store_in(plane(K, 1), v);
+        if constexpr (PRO) patch_step(s + 1);
+        store_in(plane(K, 1), corrected(s + 1, v));
         if constexpr (BYL) store_in(yplane(K, 1), yv);
         v = load_in(s + 2);
         if constexpr (BYL) yv = load_y(s + 2);
@@ -317,12 +366,29 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         }
     };
 
-    store_in(plane(0, -1), load_in(sbeg - 1));
-    store_in(plane(0, 0), load_in(sbeg));
+    if constexpr (PRO) {
+        // the planes the prologue and the first step read; then the window of
+        // plane sbeg - 2 (moved to sbeg - 1 by the first use)
+        for (int c = hu_of(sbeg - 1) - 1; c <= hu_of(sbeg + 1); ++c) patch_store(c, patch_load(c));
+        lds_barrier();
+        if constexpr (WIN) {
+            // planes hu - 1, hu of plane sbeg - 2: h - 1, h (sbeg - 1 even) or h - 2, h - 1
+            // (sbeg - 1 odd: the first move drops W0, set to h - 1 here)
+            const int h = hu_of(sbeg - 1);
+            W0 = coarse_xy(h - 1);
+            W1 = ((sbeg - 1) & 1) ? W0 : coarse_xy(h);
+        }
+    }
+    store_in(plane(0, -1), corrected(sbeg - 1, load_in(sbeg - 1)));
+    store_in(plane(0, 0), corrected(sbeg, load_in(sbeg)));
     v = load_in(sbeg + 1);
     if constexpr (BYL) {
         store_in(yplane(0, 0), load_y(sbeg));
         yv = load_y(sbeg + 1);
+    }
+    if constexpr (PRO) {
+        Qn = patch_load(hu_of(sbeg + 2));
+        lds_barrier();  // the reads above before the first step's patch store
     }
     Coef R0, R1, R2, R3, R4, R5, R6;
     load_coef(sbeg, R0);
@@ -410,12 +476,14 @@ hipError_t launch_sweep2(const T* bx, const T* by, const T* bz, Dims d, T h2, co
     const int c0 = order == 0 ? 0 : 1, zi = zero_in ? 1 : 0;
     if (sweep2_wide(d)) {
         const Sweep2Launch g = sweep2_geom<64, TY>(d);
-        hipExtLaunchKernelGGL(k_sweep2_fused<T, 64, TY>, dim3(g.blocks), dim3(Sweep2Geom<64, TY, sizeof(T)>::NT), 0, s,
-                              ev0, ev1, 0, bx, by, bz, b, in, out, d, h2, c0, zi, g.zc, g.ntx, g.nty, ec, cd);
+        auto k = ec ? k_sweep2_fused<T, 64, TY, true> : k_sweep2_fused<T, 64, TY, false>;
+        hipExtLaunchKernelGGL(k, dim3(g.blocks), dim3(Sweep2Geom<64, TY, sizeof(T)>::NT), 0, s, ev0, ev1, 0, bx, by,
+                              bz, b, in, out, d, h2, c0, zi, g.zc, g.ntx, g.nty, ec, cd);
     } else if constexpr (sizeof(T) == 4) {
         const Sweep2Launch g = sweep2_geom<32, TY>(d);
-        hipExtLaunchKernelGGL(k_sweep2_fused<T, 32, TY>, dim3(g.blocks), dim3(Sweep2Geom<32, TY>::NT), 0, s, ev0, ev1,
-                              0, bx, by, bz, b, in, out, d, h2, c0, zi, g.zc, g.ntx, g.nty, ec, cd);
+        auto k = ec ? k_sweep2_fused<T, 32, TY, true> : k_sweep2_fused<T, 32, TY, false>;
+        hipExtLaunchKernelGGL(k, dim3(g.blocks), dim3(Sweep2Geom<32, TY>::NT), 0, s, ev0, ev1, 0, bx, by, bz, b, in,
+                              out, d, h2, c0, zi, g.zc, g.ntx, g.nty, ec, cd);
     } else {
         return hipErrorInvalidValue;  // FP64 pairs only on 64-wide grids (sweep2_ok)
     }

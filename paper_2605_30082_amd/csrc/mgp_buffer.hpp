@@ -83,4 +83,21 @@ __device__ __forceinline__ T bload1(__amdgpu_buffer_rsrc_t r, unsigned voff, uns
     return bload((T*)nullptr, r, voff, soff);
 }
 
+// Vector stores through a buffer resource (32-bit lane offset, plane offset in
+// an SGPR): no 64-bit per-lane address is kept live for the output arrays.
+__device__ __forceinline__ void bstore1f(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, float2 v, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, voff,
+                                          soff, 0);
+}
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, double2 v, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r,
+                                           voff, soff, 0);
+}
+
 }  // namespace mgp

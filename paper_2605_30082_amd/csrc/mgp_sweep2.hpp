@@ -94,6 +94,7 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     using G = Sweep2Geom<TX, TY, sizeof(T)>;
     using T2 = typename Vec2<T>::type;
     constexpr bool BYL = sizeof(T) == 8;  // y-face coefficients in LDS planes
+    using Fz = std::integral_constant<bool, false>;  // step flavour with the z tests
     __shared__ T slot[G::SLOTS * G::PLANE];
     __shared__ T yslot[BYL ? G::SLOTS * G::PLANE : 1];
     const int nb = (int)gridDim.x, bid = (int)blockIdx.x;
@@ -120,7 +121,7 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     const auto r_by = make_rsrc(by, (unsigned)(n_fy(d) * sizeof(T)));
     const auto r_bz = make_rsrc(bz, (unsigned)(n_fz(d) * sizeof(T)));
     const auto r_in = make_rsrc(in, (unsigned)(ncell * sizeof(T)));
-    const auto r_null = make_rsrc(in, 0u);
+    const auto r_out = make_rsrc(out, (unsigned)(ncell * sizeof(T)));
     const unsigned oin = inside ? (unsigned)(gy * d.nx + gx0) * sizeof(T) : kOutside;
     const unsigned oc = coef_row ? (unsigned)(gy * d.nx + gx0) * sizeof(T) : kOutside;
     const unsigned ofx = coef_row ? (unsigned)(gy * (d.nx + 2) + gx0) * sizeof(T) : kOutside;
@@ -161,10 +162,11 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     // patch positions of the pair's coarse cell (I, J) and of (I, Jn), Jn the
     // coarse row on the pair's side; I - 1 and I + 1 lie beside them
     const int pm0 = ((gy >> 1) - (y0 / 2 - 3)) * CPX + ((gx0 >> 1) - (x0 / 2 - 3));
-    const int pm1 = pm0 + ((gy & 1) ? CPX : -CPX);
+    const int dpm = (gy & 1) ? CPX : -CPX;  // pm1 = pm0 + dpm
     // x- and y-interpolated correction of coarse plane c for the pair's two cells
     auto coarse_xy = [&](int c) -> T2 {
         const T* C = cbase(c);
+        const int pm1 = pm0 + dpm;
         const T m0 = C[pm0], m1 = C[pm1];
         const T a0 = pro_lerp(m0, C[pm0 - 1]), a1 = pro_lerp(m0, C[pm0 + 1]);
         const T b0 = pro_lerp(m1, C[pm1 - 1]), b1 = pro_lerp(m1, C[pm1 + 1]);
@@ -199,10 +201,10 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     };
     // the iterate of fine plane z with the correction added: fine plane 2K
     // takes coarse planes K and K-1, plane 2K+1 K and K+1 (clamped)
-    auto corrected = [&](int z, T2 v) -> T2 {
+    auto corrected = [&](auto fullc, int z, T2 v) -> T2 {
         if constexpr (PRO) {
             if constexpr (WIN) move_window(z);
-            if (inside && z >= 0 && z < d.nz) {
+            if (inside && (decltype(fullc)::value || (z >= 0 && z < d.nz))) {
                 T2 hi, lo;
                 if constexpr (WIN) {
                     hi = W1;
@@ -219,9 +221,12 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
         }
         return v;
     };
-    auto load_in = [&](int z) -> T2 {
-        const bool zv = !zero_in && z >= 0 && z < d.nz;
-        return bload2<T>(zv ? r_in : r_null, oin, cpl(z) * psz);
+    auto load_in = [&](auto fullc, int z) -> T2 {
+        if constexpr (decltype(fullc)::value) {
+            if (PRO || !zero_in) return bload2<T>(r_in, oin, (unsigned)z * psz);
+        }
+        const bool zv = !(PRO ? false : zero_in) && z >= 0 && z < d.nz;
+        return bload2<T>(r_in, zv ? oin : kOutside, cpl(z) * psz);
     };
     // LDS plane of z-step position K (0..6) and plane offset dz from the step's
     // plane s: the loop is unrolled seven times, so slot numbers are constants
@@ -273,10 +278,10 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     // Half-sweep of the colour-`col` cell of the pair on plane z (LDS planes
     // Pm, P0, Pp hold z-1, z, z+1), if that cell lies in the tile + r ring and
     // in the domain; the value goes to `v`, its LDS index to `li`.
-    auto relax = [&](int z, int col, int r, const T* Pm, const T* P0, const T* Pp, const T* Y0, const Coef& C,
-                     const Coef& Cup, bool& ok, int& li, T& v) {
+    auto relax = [&](auto fullc, int z, int col, int r, const T* Pm, const T* P0, const T* Pp, const T* Y0,
+                     const Coef& C, const Coef& Cup, bool& ok, int& li, T& v) {
         const int odd = gyp ^ ((z + col) & 1);
-        ok = z >= 0 && z < d.nz && ((ring >> (2 * r + odd)) & 1);
+        ok = (decltype(fullc)::value || (z >= 0 && z < d.nz)) && ((ring >> (2 * r + odd)) & 1);
         li = odd ? lo : le;
         if (!ok) return;
         // x-neighbours: (even cell) odd cells x-1, x+1 = lo-1, lo; (odd cell) even cells le, le+1
@@ -317,52 +322,53 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     // z takes its upper z-faces from the set of plane z+1.  The iterate of
     // plane s+2 is loaded first in the step and written to LDS at the next step.
     T2 v, yv;
-    auto step = [&](auto Kc, int s, Coef& Ln, const Coef& Cp1, const Coef& Cs, const Coef& Cm1, const Coef& Cm2,
-                    const Coef& Cm3, const Coef& Cm4) {
+    auto step = [&](auto Kc, auto fullc, int s, Coef& Ln, const Coef& Cp1, const Coef& Cs, const Coef& Cm1,
+                    const Coef& Cm2, const Coef& Cm3, const Coef& Cm4) {
         constexpr int K = decltype(Kc)::value;
+        constexpr bool FULL = decltype(fullc)::value;
         if constexpr (PRO) patch_step(s + 1);
-        store_in(plane(K, 1), corrected(s + 1, v));
+        store_in(plane(K, 1), corrected(fullc, s + 1, v));
         if constexpr (BYL) store_in(yplane(K, 1), yv);
-        v = load_in(s + 2);
+        v = load_in(fullc, s + 2);
         if constexpr (BYL) yv = load_y(s + 2);
         load_coef(s + 2, Ln);
         lds_barrier();
         // phase 1: A1 on plane s and A2 on plane s-3 (disjoint planes and states)
-        if (s <= z1 + 2) {
+        if (FULL || s <= z1 + 2) {
             bool ok;
             int li;
             T a = (T)0;
-            relax(s, cA, 3, plane(K, -1), plane(K, 0), plane(K, 1), yplane(K, 0), Cs, Cp1, ok, li, a);
+            relax(fullc, s, cA, 3, plane(K, -1), plane(K, 0), plane(K, 1), yplane(K, 0), Cs, Cp1, ok, li, a);
             if (ok) plane(K, 0)[li] = a;
         }
-        if (s - 3 >= z0 - 1 && s - 3 <= z1) {
+        if (FULL || (s - 3 >= z0 - 1 && s - 3 <= z1)) {
             bool ok;
             int li;
             T a = (T)0;
-            relax(s - 3, cA, 1, plane(K, -4), plane(K, -3), plane(K, -2), yplane(K, -3), Cm3, Cm2, ok, li, a);
+            relax(fullc, s - 3, cA, 1, plane(K, -4), plane(K, -3), plane(K, -2), yplane(K, -3), Cm3, Cm2, ok, li, a);
             if (ok) plane(K, -3)[li] = a;
         }
         lds_barrier();
         // phase 2: B1 on plane s-1 and B2 on plane s-4 (B2 written to memory)
-        if (s - 1 >= z0 - 2 && s - 1 <= z1 + 1) {
+        if (FULL || (s - 1 >= z0 - 2 && s - 1 <= z1 + 1)) {
             bool ok;
             int li;
             T bv = (T)0;
-            relax(s - 1, cB, 2, plane(K, -2), plane(K, -1), plane(K, 0), yplane(K, -1), Cm1, Cs, ok, li, bv);
+            relax(fullc, s - 1, cB, 2, plane(K, -2), plane(K, -1), plane(K, 0), yplane(K, -1), Cm1, Cs, ok, li, bv);
             if (ok) plane(K, -1)[li] = bv;
         }
         const int zb = s - 4;
-        if (zb >= z0 && core) {
+        if ((FULL || zb >= z0) && core) {
             bool ok;
             int li;
             T bv = (T)0;
-            relax(zb, cB, 0, plane(K, -5), plane(K, -4), plane(K, -3), yplane(K, -4), Cm4, Cm3, ok, li, bv);
+            relax(fullc, zb, cB, 0, plane(K, -5), plane(K, -4), plane(K, -3), yplane(K, -4), Cm4, Cm3, ok, li, bv);
             const bool bodd = li == lo;
             const T av = plane(K, -4)[bodd ? le : lo];
             T2 o;
             o.x = bodd ? av : bv;
             o.y = bodd ? bv : av;
-            *reinterpret_cast<T2*>(out + (long)zb * d.nx * d.ny + (long)gy * d.nx + gx0) = o;
+            bstore2(r_out, o, oin, (unsigned)zb * psz);
         }
     };
 
@@ -379,9 +385,9 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
             W1 = ((sbeg - 1) & 1) ? W0 : coarse_xy(h);
         }
     }
-    store_in(plane(0, -1), corrected(sbeg - 1, load_in(sbeg - 1)));
-    store_in(plane(0, 0), corrected(sbeg, load_in(sbeg)));
-    v = load_in(sbeg + 1);
+    store_in(plane(0, -1), corrected(Fz{}, sbeg - 1, load_in(Fz{}, sbeg - 1)));
+    store_in(plane(0, 0), corrected(Fz{}, sbeg, load_in(Fz{}, sbeg)));
+    v = load_in(Fz{}, sbeg + 1);
     if constexpr (BYL) {
         store_in(yplane(0, 0), load_y(sbeg));
         yv = load_y(sbeg + 1);
@@ -401,21 +407,38 @@ k_sweep2_fused(const T* __restrict__ bx, const T* __restrict__ by, const T* __re
     using I4 = std::integral_constant<int, 4>;
     using I5 = std::integral_constant<int, 5>;
     using I6 = std::integral_constant<int, 6>;
-    // step(K, s, Ln = set(s+2), set(s+1), set(s), set(s-1), set(s-2), set(s-3), set(s-4))
-    for (int s = sbeg; s <= send; s += 7) {
-        step(I0{}, s, R2, R1, R0, R6, R5, R4, R3);
+    // step(K, full, s, Ln = set(s+2), set(s+1), set(s), set(s-1), set(s-2), set(s-3), set(s-4)).
+    // Steps s in [z0 + 4, min(z1 + 2, nz - 3)] touch planes s-5 .. s+2 all
+    // inside the grid and run every stage: they take the "full" instance,
+    // without the z tests and the branches around the stages.
+    const int flo = z0 + 4, fhi = min(z1 + 2, d.nz - 3);
+    using Ft = std::integral_constant<bool, true>;
+    auto seven = [&](auto fullc, int s) {
+        step(I0{}, fullc, s, R2, R1, R0, R6, R5, R4, R3);
+        step(I1{}, fullc, s + 1, R3, R2, R1, R0, R6, R5, R4);
+        step(I2{}, fullc, s + 2, R4, R3, R2, R1, R0, R6, R5);
+        step(I3{}, fullc, s + 3, R5, R4, R3, R2, R1, R0, R6);
+        step(I4{}, fullc, s + 4, R6, R5, R4, R3, R2, R1, R0);
+        step(I5{}, fullc, s + 5, R0, R6, R5, R4, R3, R2, R1);
+        step(I6{}, fullc, s + 6, R1, R0, R6, R5, R4, R3, R2);
+    };
+    int s = sbeg;
+    for (; s < flo && s + 6 <= send; s += 7) seven(Fz{}, s);
+    for (; s + 6 <= fhi; s += 7) seven(Ft{}, s);
+    for (; s <= send; s += 7) {
+        step(I0{}, Fz{}, s, R2, R1, R0, R6, R5, R4, R3);
         if (s + 1 > send) break;
-        step(I1{}, s + 1, R3, R2, R1, R0, R6, R5, R4);
+        step(I1{}, Fz{}, s + 1, R3, R2, R1, R0, R6, R5, R4);
         if (s + 2 > send) break;
-        step(I2{}, s + 2, R4, R3, R2, R1, R0, R6, R5);
+        step(I2{}, Fz{}, s + 2, R4, R3, R2, R1, R0, R6, R5);
         if (s + 3 > send) break;
-        step(I3{}, s + 3, R5, R4, R3, R2, R1, R0, R6);
+        step(I3{}, Fz{}, s + 3, R5, R4, R3, R2, R1, R0, R6);
         if (s + 4 > send) break;
-        step(I4{}, s + 4, R6, R5, R4, R3, R2, R1, R0);
+        step(I4{}, Fz{}, s + 4, R6, R5, R4, R3, R2, R1, R0);
         if (s + 5 > send) break;
-        step(I5{}, s + 5, R0, R6, R5, R4, R3, R2, R1);
+        step(I5{}, Fz{}, s + 5, R0, R6, R5, R4, R3, R2, R1);
         if (s + 6 > send) break;
-        step(I6{}, s + 6, R1, R0, R6, R5, R4, R3, R2);
+        step(I6{}, Fz{}, s + 6, R1, R0, R6, R5, R4, R3, R2);
     }
 }
 

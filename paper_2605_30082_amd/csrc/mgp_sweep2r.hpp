@@ -33,18 +33,6 @@
 
 namespace mgp {
 
-// Vector stores through a buffer resource (32-bit lane offset, plane offset in
-// an SGPR): no 64-bit per-lane address is kept live for the output arrays.
-__device__ __forceinline__ void bstore1f(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
-}
-__device__ __forceinline__ void bstore2f(__amdgpu_buffer_rsrc_t r, float2 v, unsigned voff, unsigned soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, voff,
-                                          soff, 0);
-}
-
 // Launch contract: nx even and >= 64, ny even and >= TY, nz even, zc even,
 // every array below 2^31 bytes, grid = ntx * nty * ceil(nz / zc) blocks of
 // Sweep2Geom<64, TY>::NT threads; coarse has the (nx/2, ny/2, nz/2) layout.
@@ -240,7 +228,7 @@ k_sweep2_restrict(const float* __restrict__ bx, const float* __restrict__ by, co
                 T2 o;
                 o.x = bodd ? av : bv;
                 o.y = bodd ? bv : av;
-                bstore2f(r_out, o, oc, (unsigned)zb * psz);
+                bstore2(r_out, o, oc, (unsigned)zb * psz);
             }
         }
         // A-cell of plane s-5 (planes s-6, s-5 are final and untouched in this

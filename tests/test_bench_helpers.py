@@ -41,11 +41,12 @@ def test_stored_oracle_samples_are_found_for_their_workload_only(workload, n, dr
         assert os.path.basename(path) == f"{workload}{n}_oracle.txt"
 
 
-def test_traffic_record_applies_to_its_kernel_and_size_only():
-    k = bench.TRAFFIC["kernel"]
-    assert bench.measured_traffic(k, 256) is None
+def test_traffic_record_applies_to_its_kernels_and_size_only():
     assert bench.measured_traffic("mgp::k_resid<float, 1, false>", 512) is None
-    assert bench.TRAFFIC["kernel"] == bench.KERNEL_SYMBOLS[("sweep2", "mixed")]
+    known = {bench.kernel_symbol("sweep2", "mixed", "density"), bench.kernel_symbol("outer_update", "mixed", "density")}
+    for k in bench.TRAFFIC["kernels"]:
+        assert k in known
+        assert bench.measured_traffic(k, 256) is None
     assert bench.TRAFFIC["fetch_scale"] > 0 and bench.TRAFFIC["write_scale"] > 0
 
 

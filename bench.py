@@ -80,14 +80,14 @@ def kernel_symbol(name, precision, coefficients):
 TRAFFIC = {
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_resid.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "7ebf9b3604fcbe540b4a5c8181067db9747e4dcb7a0e16480abbfced972cae08",
+    "sha256": "21a996913d7d4eb03f6be88212f04a4b14b0cf62bdc384fd9cd1321bcb66fd82",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     "kernels": {
-        "mgp::k_sweep2_fused<float, 64, 16, true>": {"fetch_kib": 584092.5, "write_kib": 149760.1,
-                                                     "finest_fetch_kib": 2081322.9, "finest_write_kib": 524288.5},
-        "mgp::k_resid<double, 2, true>": {"fetch_kib": 2031199.9, "write_kib": 1572935.6,
-                                          "finest_fetch_kib": 2031199.9, "finest_write_kib": 1572935.6},
+        "mgp::k_sweep2_fused<float, 64, 16, true>": {"fetch_kib": 583632.3, "write_kib": 149760.1,
+                                                     "finest_fetch_kib": 2080827.3, "finest_write_kib": 524288.5},
+        "mgp::k_resid<double, 2, true>": {"fetch_kib": 2069589.9, "write_kib": 1572872.5,
+                                          "finest_fetch_kib": 2069589.9, "finest_write_kib": 1572872.5},
     },
 }
 

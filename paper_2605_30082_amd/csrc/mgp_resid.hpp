@@ -307,11 +307,15 @@ inline ResGeom res_geom(const Dims& d)
     g.ntx = (d.nx + 63) / 64;
     g.nty = (d.ny + kResTY - 1) / kResTY;
     const int tiles = g.ntx * g.nty;
-    int nzc = (2048 + tiles - 1) / tiles;
+    // about 256 blocks, one per compute unit, each a long chunk (each chunk
+    // re-reads two planes and restarts its pipeline; at 512^3 the outer update
+    // took 1.14 / 1.10 / 1.07 / 1.05 / 1.70 ms with 2048 / 1024 / 512 / 256 /
+    // 128 blocks)
+    int nzc = (256 + tiles - 1) / tiles;
     int zc = (d.nz + nzc - 1) / nzc;
-    // at least 8 planes (each chunk re-reads two planes and restarts its
-    // pipeline) unless that leaves fewer than 1024 blocks: small grids take
-    // chunks of 2 (at 64^3 / 128^3: 5.9 / 10.0 against 13.5 / 13.6 us)
+    // at least 8 planes unless that leaves fewer than 1024 blocks: small grids
+    // take short chunks (at 64^3 / 128^3 chunks of 2 took 5.9 / 10.0 against
+    // 13.5 / 13.6 us with 8)
     const int z8 = zc < 8 ? 8 : zc;
     if ((long)tiles * ((d.nz + z8 - 1) / z8) >= 1024) zc = z8;
     if (zc < 2) zc = 2;

@@ -80,7 +80,7 @@ def kernel_symbol(name, precision, coefficients):
 TRAFFIC = {
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_resid.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "21a996913d7d4eb03f6be88212f04a4b14b0cf62bdc384fd9cd1321bcb66fd82",
+    "sha256": "0b6f4acfaa281401f0c2f2ec7533c9dca2551bbf8e1711efce2665dd5b37ab47",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     "kernels": {

@@ -68,13 +68,13 @@ struct Sweep2Geom {
 // in + P ec, P the trilinear prolongation, so the separate prolongation pass
 // (read in, write in) goes away.  The value is the one k_prolong_tiled writes:
 // pro_lerp along x, then y, then z.  Fine plane z lies between coarse planes
-// (z - 1) / 2 and (z + 1) / 2 (clamped), so the z march needs a window of two
-// coarse planes that moves up by one plane every second fine plane.  Per pair
-// the window holds the x- and y-interpolated values of its two planes; the six
-// coarse loads of the plane that enters next are issued when the window moves,
-// two steps before they are interpolated, and the correction is added when the
-// fine plane goes to LDS, a step after its load: no load is waited for in the
-// step that issues it.
+// (z - 1) / 2 and (z + 1) / 2 (clamped).  Each step the block loads its patch
+// of one coarse plane (one value per thread), stores the patch of the plane
+// that enters next into one of three LDS slots a step later, and each pair
+// interpolates its x and y values from LDS; the correction is added when the
+// fine plane goes to LDS, a step after its load.  No load result passes through
+// a conditional assignment: a copy made where a branch merges would wait for
+// the load, and with it for every load in flight, in the step that issues it.
 //
 // FP64: the coefficients of seven planes would not fit the registers of 14
 // waves, so the FP64 instance takes 64 x 8 tiles (9 waves) and keeps the

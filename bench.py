@@ -80,7 +80,7 @@ def kernel_symbol(name, precision, coefficients):
 TRAFFIC = {
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_resid.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "0b6f4acfaa281401f0c2f2ec7533c9dca2551bbf8e1711efce2665dd5b37ab47",
+    "sha256": "e26dd43a342eff5550e040c53bc2ed84bae0939f2165d3cf02b069a35609b605",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     "kernels": {

@@ -781,12 +781,19 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
     const long n = F.n;
     const bool zero_guess = (c->opts.flags & MG_FLAG_ZERO_GUESS) != 0;
 
-    // b0 = rhs - mean(rhs); ||b0||^2
+    // b0 = rhs - mean(rhs); ||b0||^2.  A mixed solve from p = 0 starts from the
+    // FP32 residual b0 (L 0 = 0 exactly): the same pass writes it.
+    const bool cast_b0 = c->mixed && zero_guess && !(c->opts.flags & MG_FLAG_FCG) &&
+                         res_tiled_ok(F.d, sizeof(double));
     k_sum<double><<<kReduceBlocks, kBlock, 0, c->stream>>>(rhs, n, c->partials);
     CHECK_LAUNCH(c);
     TRY(reduce_to(c, kReduceBlocks, 0));
-    k_sub_scalar_norm<<<kReduceBlocks, kBlock, 0, c->stream>>>(rhs, n, c->scal, 0, 1.0 / (double)n, c->b0,
-                                                               c->partials);
+    if (cast_b0)
+        k_sub_scalar_norm<true><<<kReduceBlocks, kBlock, 0, c->stream>>>(rhs, n, c->scal, 0, 1.0 / (double)n,
+                                                                         c->b0, F.f32.b, c->partials);
+    else
+        k_sub_scalar_norm<false><<<kReduceBlocks, kBlock, 0, c->stream>>>(rhs, n, c->scal, 0, 1.0 / (double)n,
+                                                                          c->b0, nullptr, c->partials);
     CHECK_LAUNCH(c);
     TRY(reduce_to(c, kReduceBlocks, 1));
     TRY(fetch_scalars(c, 2));
@@ -863,8 +870,7 @@ int solve_impl(mg_ctx* c, const double* rhs, double* p, double tol, mg_stats* st
         // initial residual in FP64, cast to FP32.  From p = 0 it is b0 itself
         // (L 0 = 0 exactly) and rr = 1: a cast, and the first update reads no p.
         bool p_zero = false;
-        if (zero_guess && res_tiled_ok(F0.d, sizeof(double))) {
-            TRY(convert<double, float>(c, c->b0, n, r32));
+        if (cast_b0) {  // r32 = b0, written with it
             rr = 1.0;
             p_zero = true;
         } else {

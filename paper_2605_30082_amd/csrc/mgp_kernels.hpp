@@ -76,28 +76,53 @@ __global__ void k_reduce_final(const double* __restrict__ partials, int count, d
     if (threadIdx.x == 0) out[slot] = v;
 }
 
+// The reductions over a whole array run a fixed grid (kReduceBlocks), so each
+// thread walks many elements: it loads kReduceUnroll of them before adding
+// any (that many loads in flight instead of one), in the order of the plain
+// grid-stride loop, so the sums do not depend on the unrolling.
+constexpr int kReduceUnroll = 8;
+
 template <typename T>
 __global__ void k_sum(const T* __restrict__ x, long n, double* __restrict__ partials)
 {
+    constexpr int U = kReduceUnroll;
+    const long stride = (long)gridDim.x * kBlock;
     double v = 0.0;
-    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock)
-        v += (double)x[c];
+    long c = (long)blockIdx.x * kBlock + threadIdx.x;
+    for (; c + (U - 1) * stride < n; c += U * stride) {
+        T a[U];
+        for (int u = 0; u < U; ++u) a[u] = x[c + u * stride];
+        for (int u = 0; u < U; ++u) v += (double)a[u];
+    }
+    for (; c < n; c += stride) v += (double)x[c];
     v = block_sum(v);
     if (threadIdx.x == 0) partials[blockIdx.x] = v;
 }
 
-// y = x - scal[slot] * scale, partial sums of y^2
+// y = x - scal[slot] * scale (and, with F32, y32 = y rounded to FP32), partial
+// sums of y^2
+template <bool F32>
 __global__ void k_sub_scalar_norm(const double* __restrict__ x, long n, const double* __restrict__ scal,
-                                  int slot, double scale, double* __restrict__ y,
+                                  int slot, double scale, double* __restrict__ y, float* __restrict__ y32,
                                   double* __restrict__ partials)
 {
+    constexpr int U = kReduceUnroll;
+    const long stride = (long)gridDim.x * kBlock;
     const double mu = scal[slot] * scale;
     double v = 0.0;
-    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
-        double t = x[c] - mu;
-        y[c] = t;
+    auto put = [&](long i, double xi) {
+        const double t = xi - mu;
+        y[i] = t;
+        if constexpr (F32) y32[i] = (float)t;
         v += t * t;
+    };
+    long c = (long)blockIdx.x * kBlock + threadIdx.x;
+    for (; c + (U - 1) * stride < n; c += U * stride) {
+        double a[U];
+        for (int u = 0; u < U; ++u) a[u] = x[c + u * stride];
+        for (int u = 0; u < U; ++u) put(c + u * stride, a[u]);
     }
+    for (; c < n; c += stride) put(c, x[c]);
     v = block_sum(v);
     if (threadIdx.x == 0) partials[blockIdx.x] = v;
 }

@@ -390,3 +390,43 @@ def test_adjoint_and_face_grad_match_oracle():
     for a, r in zip(s.face_grad(T(lam_n), T(p_n)), oracle.face_grad(lam_n, p_n, wl.h)):
         np.testing.assert_allclose(N(a), r, rtol=1e-14, atol=1e-300)
     s.close()
+
+
+def test_solve_reductions_over_grouped_and_remaining_cells():
+    """Mean removal and norms on a grid of 192 x 128 x 128 cells (3.1M): the
+    whole-array reductions walk it in strides of their fixed grid, eight strides
+    at a time while eight remain and one at a time after that, so both parts
+    run.  A smooth density field (1.2 .. 1000) and a rhs with mean 3.  FP64
+    runs in lockstep with the oracle stopped by the same rule; the mixed solve
+    (whose FP32 residual the mean-removal pass writes) meets the tolerance in
+    the oracle's own residual; both results have zero mean, and the rhs shifted
+    by a constant gives the same solution."""
+    dims = nx, ny, nz = (192, 128, 128)
+    zz, yy, xx = np.meshgrid((np.arange(nz) + 0.5) / nz, (np.arange(ny) + 0.5) / ny, (np.arange(nx) + 0.5) / nx,
+                             indexing="ij")
+    s3 = np.sin(2 * np.pi * xx) * np.sin(2 * np.pi * yy) * np.sin(2 * np.pi * zz)
+    rho = np.sqrt(1.2 * 1000.0) * np.exp(0.5 * np.log(1000.0 / 1.2) * s3)
+    beta = oracle.face_coeffs(rho)
+    rhs = np.random.default_rng(8).standard_normal((nz, ny, nx)) + 3.0
+    h = 1.0 / nx
+    exact = oracle.solve(beta, rhs, h, tol=1e-12)
+    ref10 = oracle.solve(beta, rhs, h, tol=1e-10)
+    b0 = rhs - rhs.mean()
+    for precision in ("fp64", "mixed"):
+        note(f"reductions {dims} {precision}")
+        with make_solver(beta, h, precision=precision, zero_guess=True) as s:
+            p, st = s.solve(T(rhs), 1e-10)
+            p2, st2 = s.solve(T(rhs + 5.0), 1e-10)
+        pg, pg2 = N(p), N(p2)
+        rr = np.linalg.norm(oracle.residual(beta, b0, pg, h)) / np.linalg.norm(b0)
+        note(f"  cycles {st.cycles} (oracle {ref10.cycles}) rr {rr:.3e} err {rel_l2(pg, exact.p):.3e} "
+             f"shifted {rel_l2(pg2, pg):.3e}")
+        assert st.status == S.L.MG_OK and st.rel_res <= 1e-10 and rr <= 1.0001e-10
+        assert abs(pg.mean()) <= 1e-13 * np.sqrt(np.mean(pg ** 2))
+        assert abs(st.rhs_mean_removed - rhs.mean()) <= 1e-13 * abs(rhs.mean())
+        if precision == "fp64":
+            assert st.cycles == ref10.cycles and rel_l2(pg, ref10.p) < 1e-11
+            assert rel_l2(pg2, pg) < 1e-11
+        else:
+            assert st.cycles <= ref10.cycles + 2 and rel_l2(pg, exact.p) < 1e-8
+            assert rel_l2(pg2, pg) < 1e-8

@@ -80,7 +80,7 @@ def kernel_symbol(name, precision, coefficients):
 TRAFFIC = {
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_resid.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "e26dd43a342eff5550e040c53bc2ed84bae0939f2165d3cf02b069a35609b605",
+    "sha256": "58486fee0ea2a49f26d3dbf948e613e704fe8c4857cf84f98f82cfa8eff497fa",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     "kernels": {

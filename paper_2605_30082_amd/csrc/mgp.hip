@@ -455,12 +455,15 @@ int vcycle_tail(mg_ctx* c, int l, T** x, T** t, const T* b, bool zero_init, int 
     long faces = 0;
     for (int k = l; k < c->nlev - 1; ++k) faces += n_fx(c->lev[k].d) + n_fy(c->lev[k].d) + n_fz(c->lev[k].d);
     const int zi = zero_init ? 1 : 0;
-    if (sizeof(T) == 4 && faces <= kTailFaceLds)
-        k_vcycle_tail<T, sizeof(T) == 4><<<1, kTailNT, 0, c->stream>>>(tail_tab<T>(c), l, c->nlev, c->G, *x, *t, b,
-                                                                       pre, post, zi, pre_done);
-    else
-        k_vcycle_tail<T, false><<<1, kTailNT, 0, c->stream>>>(tail_tab<T>(c), l, c->nlev, c->G, *x, *t, b, pre,
-                                                              post, zi, pre_done);
+    bool p2 = true;  // every level's x and y sizes powers of two: index arithmetic by shifts
+    for (int k = l; k < c->nlev; ++k) {
+        const Dims& d = c->lev[k].d;
+        p2 = p2 && (d.nx & (d.nx - 1)) == 0 && (d.ny & (d.ny - 1)) == 0;
+    }
+    const bool flds = sizeof(T) == 4 && faces <= kTailFaceLds;
+    auto k = flds ? (p2 ? k_vcycle_tail<T, sizeof(T) == 4, true> : k_vcycle_tail<T, sizeof(T) == 4, false>)
+                  : (p2 ? k_vcycle_tail<T, false, true> : k_vcycle_tail<T, false, false>);
+    k<<<1, kTailNT, 0, c->stream>>>(tail_tab<T>(c), l, c->nlev, c->G, *x, *t, b, pre, post, zi, pre_done);
     CHECK_LAUNCH(c);
     if (((pre - pre_done) + post) & 1) std::swap(*x, *t);
     return MG_OK;

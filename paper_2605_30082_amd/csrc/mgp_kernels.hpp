@@ -597,12 +597,11 @@ __device__ __forceinline__ T pro_lerp(T parent, T side)
     else return __builtin_fma(0.75, parent, 0.25 * side);
 }
 
-// x_fine += trilinear prolongation of the coarse correction e
+// x_fine += trilinear prolongation of the coarse correction e: the value at
+// fine cell (i, j, k)
 template <typename T, typename IX = long>
-__device__ inline T prolong_value(const Dims f, const Dims cd, const T* __restrict__ e, IX c)
+__device__ inline T prolong_value_at(const Dims cd, const T* __restrict__ e, int i, int j, int k)
 {
-    int i, j, k;
-    cell_of(c, f, i, j, k);
     const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
     int I1 = (i & 1) ? I0 + 1 : I0 - 1;
     int J1 = (j & 1) ? J0 + 1 : J0 - 1;
@@ -620,6 +619,15 @@ __device__ inline T prolong_value(const Dims f, const Dims cd, const T* __restri
     const T f0 = pro_lerp(e00, e10);
     const T f1 = pro_lerp(e01, e11);
     return pro_lerp(f0, f1);
+}
+
+// the same at fine cell index c
+template <typename T, typename IX = long>
+__device__ inline T prolong_value(const Dims f, const Dims cd, const T* __restrict__ e, IX c)
+{
+    int i, j, k;
+    cell_of(c, f, i, j, k);
+    return prolong_value_at<T, IX>(cd, e, i, j, k);
 }
 
 template <typename T>

@@ -15,7 +15,7 @@
 // back.  A Gauss-Seidel half-sweep reads only cells of the other colour, so
 // the sweeps run in place: the same values as the out-of-place sweeps of the
 // per-level kernels.  The prolongation and the coarse solve are the per-level
-// kernels' device functions (prolong_value, coarse_apply_block); the sweeps and
+// kernels' device functions (prolong_value_at, coarse_apply_block); the sweeps and
 // the restriction compute the same expressions in the same order, with the
 // wall terms written as +0 instead of skipped (tail_stencil), so both paths
 // give identical results bit for bit.
@@ -46,6 +46,30 @@ struct TailLevel {
     T h2;      // h^2 (sweeps)
     T inv_h2;  // 1 / h^2 (residual)
 };
+
+// Index arithmetic of the tail's loops (cell index -> coordinates): by shifts
+// and masks when every tail level's x and y sizes are powers of two (P2; the
+// tail is VALU-bound, and the divisions took a sixth of its time), else by
+// division.
+template <bool P2>
+__device__ inline void tail_divmod(int q, int n, int& quot, int& rem)
+{
+    if constexpr (P2) {
+        quot = q >> __builtin_ctz((unsigned)n);
+        rem = q & (n - 1);
+    } else {
+        quot = q / n;
+        rem = q - quot * n;
+    }
+}
+
+template <bool P2>
+__device__ inline void tail_cell_of(int q, const Dims d, int& i, int& j, int& k)
+{
+    int row;
+    tail_divmod<P2>(q, d.nx, row, i);
+    tail_divmod<P2>(row, d.ny, k, j);
+}
 
 // The per-level kernels' stencil without its wall branches.  Wall faces are
 // stored zeros at every level, so a wall term adds +0 to the diagonal and
@@ -116,7 +140,7 @@ __device__ inline T tail_restrict_cell(const T* fx, const T* fy, const T* fz, co
 
 // One sweep of x (in LDS) in place: colour c0 (treating x as 0 if zero_in),
 // then the other colour.  fx, fy, fz: the level's faces (LDS or memory).
-template <typename T>
+template <typename T, bool P2>
 __device__ void tail_sweep(const T* fx, const T* fy, const T* fz, const Dims d, T h2, const T* b, T* x, int c0,
                            int zero_in)
 {
@@ -132,10 +156,9 @@ __device__ void tail_sweep(const T* fx, const T* fy, const T* fz, const Dims d, 
 #pragma unroll
             for (int u = 0; u < kTailBatch; ++u) {
                 const int q = q0 + u * kTailNT + (int)threadIdx.x;
-                const int r = q / hx;
-                const int m = q - r * hx;
-                const int k = r / d.ny;
-                const int j = r - k * d.ny;
+                int r, m, k, j;
+                tail_divmod<P2>(q, hx, r, m);
+                tail_divmod<P2>(r, d.ny, k, j);
                 const int i = 2 * m + ((j + k + colour) & 1);
                 c[u] = -1;
                 if (q < cnt && i < d.nx) {
@@ -160,10 +183,11 @@ __device__ void tail_sweep(const T* fx, const T* fy, const T* fz, const Dims d, 
 // first (at most kTailFaceLds values together), so that no step after the
 // start reads memory except the coarsest inverse; a template flag, so that
 // every face read is an LDS read by construction.
+// P2: every level's x and y sizes are powers of two (index arithmetic by shifts).
 // Launch: one block of kTailNT threads; levels l0..nl-1 at most kTailCells
 // cells each and kTailLds together, the coarsest at most 64, nl - l0 at most
 // kTailMaxLevels.
-template <typename T, bool FLDS>
+template <typename T, bool FLDS, bool P2>
 __global__ void __launch_bounds__(kTailNT)
 k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double* __restrict__ G,
               T* x0, T* t0, const T* __restrict__ b0, int pre, int post, int zero_init, int pre_done)
@@ -232,12 +256,13 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
             for (int q = tid; q < ncell(k); q += kTailNT) x[q] = (T)0;
             __syncthreads();
         }
-        for (int s = 0; s < pre - done; ++s) tail_sweep<T>(fx, fy, fz, L.d, L.h2, b, x, 0, zi && done == 0 && s == 0);
+        for (int s = 0; s < pre - done; ++s)
+            tail_sweep<T, P2>(fx, fy, fz, L.d, L.h2, b, x, 0, zi && done == 0 && s == 0);
         const Dims cd = lv[k + 1].d;
         T* bc = bs + off(k + 1);
         for (int q = tid; q < ncell(k + 1); q += kTailNT) {
             int I, J, K;
-            cell_of(q, cd, I, J, K);
+            tail_cell_of<P2>(q, cd, I, J, K);
             bc[q] = tail_restrict_cell<T>(fx, fy, fz, L.d, L.inv_h2, b, x, I, J, K);
         }
         __syncthreads();
@@ -257,7 +282,11 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
 #pragma unroll
             for (int u = 0; u < kTailBatch; ++u) {
                 const int q = q0 + u * kTailNT + tid;
-                if (q < ncell(k)) v[u] = x[q] + prolong_value<T, int>(L.d, cd, e, q);
+                if (q < ncell(k)) {
+                    int i, j, kk;
+                    tail_cell_of<P2>(q, L.d, i, j, kk);
+                    v[u] = x[q] + prolong_value_at<T, int>(cd, e, i, j, kk);
+                }
             }
 #pragma unroll
             for (int u = 0; u < kTailBatch; ++u) {
@@ -266,7 +295,7 @@ k_vcycle_tail(const TailLevel<T>* __restrict__ tab, int l0, int nl, const double
             }
         }
         __syncthreads();
-        for (int s = 0; s < post; ++s) tail_sweep<T>(fx, fy, fz, L.d, L.h2, b, x, 1, 0);
+        for (int s = 0; s < post; ++s) tail_sweep<T, P2>(fx, fy, fz, L.d, L.h2, b, x, 1, 0);
     }
     T* out = (((pre - pre_done) + post) & 1) ? t0 : x0;
     for (int q = tid; q < ncell(0); q += kTailNT) out[q] = xs[q];

@@ -49,8 +49,8 @@ struct TailLevel {
 
 // Index arithmetic of the tail's loops (cell index -> coordinates): by shifts
 // and masks when every tail level's x and y sizes are powers of two (P2; the
-// tail is VALU-bound, and the divisions took a sixth of its time), else by
-// division.
+// tail is VALU-bound, and the divisions took about a quarter of its time),
+// else by division.
 template <bool P2>
 __device__ inline void tail_divmod(int q, int n, int& quot, int& rem)
 {

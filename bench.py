@@ -80,7 +80,7 @@ def kernel_symbol(name, precision, coefficients):
 TRAFFIC = {
     "n": 512,
     "sources": ["mgp_sweep2.hpp", "mgp_resid.hpp", "mgp_buffer.hpp", "mgp_kernels.hpp", "mgp.hip"],
-    "sha256": "58486fee0ea2a49f26d3dbf948e613e704fe8c4857cf84f98f82cfa8eff497fa",
+    "sha256": "f0c904a9c4a240016f84b6a58d2b78afc01918f19862765e36771479cca1fc1c",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     "kernels": {

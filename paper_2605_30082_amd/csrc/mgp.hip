@@ -406,8 +406,8 @@ int residual_restrict(mg_ctx* c, int l, const T* b, const T* x, T* bc)
                               (T)(1.0 / (L.h * L.h)), g.zc, g.ntx, g.nty, (T*)nullptr, (float*)nullptr, bc,
                               (double*)nullptr, (const T*)nullptr);
     } else {
-        k_residual_restrict<T><<<grid_for(C.n), kBlock, 0, c->stream>>>(B.bx, B.by, B.bz, L.d, C.d,
-                                                                       (T)(1.0 / (L.h * L.h)), b, x, bc);
+        k_residual_restrict<T><<<grid_for(8 * C.n), kBlock, 0, c->stream>>>(B.bx, B.by, B.bz, L.d, C.d,
+                                                                           (T)(1.0 / (L.h * L.h)), b, x, bc);
     }
     CHECK_LAUNCH(c);
     return MG_OK;

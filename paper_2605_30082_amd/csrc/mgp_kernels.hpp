@@ -553,35 +553,44 @@ __global__ void k_half_sweep(const T* __restrict__ bx, const T* __restrict__ by,
     half_sweep_cell<T>(bx, by, bz, d, h2, b, src, dst, zero_src, i, j, k);
 }
 
-// b_coarse = mean over the 8 children of (b - L x) (fine dims f, coarse dims c)
-template <typename T, typename IX = long>
-__device__ inline T restrict_cell(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
-                                  const Dims f, T inv_h2, const T* __restrict__ b, const T* __restrict__ x, int I,
-                                  int J, int K)
-{
-    T s = 0;
-    for (int cz = 0; cz < 2; ++cz)
-        for (int cy = 0; cy < 2; ++cy)
-            for (int cx = 0; cx < 2; ++cx) {
-                const int i = 2 * I + cx, j = 2 * J + cy, k = 2 * K + cz;
-                const IX c = ((IX)k * f.ny + j) * f.nx + i;
-                T dg, of;
-                stencil<T, T, IX>(bx, by, bz, x, f, i, j, k, c, dg, of);
-                s += b[c] - (of - dg * x[c]) * inv_h2;
-            }
-    return s * (T)0.125;
-}
 
+// b_coarse = mean over the 8 children of (b - L x) (fine dims f, coarse dims
+// cd), the eight children of a coarse cell on eight threads of a block: each
+// forms one child's residual, and the first of the eight adds them one after
+// another, z, then y, then x (the order of the single-workgroup tail).  The
+// levels this serves are small, and one thread per coarse cell working
+// through its children in turn left most of the chip idle.  Launch: blocks of
+// kBlock threads, any grid.
 template <typename T>
-__global__ void k_residual_restrict(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz,
-                                    Dims f, Dims cd, T inv_h2, const T* __restrict__ b, const T* __restrict__ x,
-                                    T* __restrict__ bc)
+__global__ void __launch_bounds__(kBlock)
+k_residual_restrict(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz, Dims f, Dims cd,
+                    T inv_h2, const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ bc)
 {
+    constexpr int kCells = kBlock / 8;  // coarse cells per block and pass
+    __shared__ T rs[kBlock];
     const long n = (long)cd.nx * cd.ny * cd.nz;
-    for (long C = (long)blockIdx.x * kBlock + threadIdx.x; C < n; C += (long)gridDim.x * kBlock) {
-        int I, J, K;
-        cell_of(C, cd, I, J, K);
-        bc[C] = restrict_cell<T>(bx, by, bz, f, inv_h2, b, x, I, J, K);
+    const int t = (int)threadIdx.x, ch = t & 7;
+    const int cx = ch & 1, cy = (ch >> 1) & 1, cz = ch >> 2;
+    for (long C0 = (long)blockIdx.x * kCells; C0 < n; C0 += (long)gridDim.x * kCells) {
+        const long C = C0 + (t >> 3);
+        T r = 0;
+        if (C < n) {
+            int I, J, K;
+            cell_of(C, cd, I, J, K);
+            const int i = 2 * I + cx, j = 2 * J + cy, k = 2 * K + cz;
+            const long c = ((long)k * f.ny + j) * f.nx + i;
+            T dg, of;
+            stencil<T, T, long>(bx, by, bz, x, f, i, j, k, c, dg, of);
+            r = b[c] - (of - dg * x[c]) * inv_h2;
+        }
+        rs[t] = r;
+        __syncthreads();
+        if (ch == 0 && C < n) {
+            T s = 0;
+            for (int q = 0; q < 8; ++q) s += rs[t + q];
+            bc[C] = s * (T)0.125;
+        }
+        __syncthreads();
     }
 }
 

@@ -119,7 +119,8 @@ __device__ inline T tail_half_sweep_value(const T* fx, const T* fy, const T* fz,
     return v;
 }
 
-// restrict_cell with tail_stencil
+// k_residual_restrict's coarse value (children added z, then y, then x) with
+// tail_stencil
 template <typename T>
 __device__ inline T tail_restrict_cell(const T* fx, const T* fy, const T* fz, const Dims f, T inv_h2, const T* b,
                                        const T* x, int I, int J, int K)

@@ -84,10 +84,10 @@ TRAFFIC = {
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     "kernels": {
-        "mgp::k_sweep2_fused<float, 64, 16, true>": {"fetch_kib": 583960.7, "write_kib": 149760.1,
-                                                     "finest_fetch_kib": 2080754.1, "finest_write_kib": 524288.5},
-        "mgp::k_resid<double, 2, true>": {"fetch_kib": 2071954.9, "write_kib": 1572872.5,
-                                          "finest_fetch_kib": 2071954.9, "finest_write_kib": 1572872.5},
+        "mgp::k_sweep2_fused<float, 64, 16, true>": {"fetch_kib": 583828.4, "write_kib": 149760.1,
+                                                     "finest_fetch_kib": 2082555.6, "finest_write_kib": 524288.5},
+        "mgp::k_resid<double, 2, true>": {"fetch_kib": 2064867.0, "write_kib": 1572872.5,
+                                          "finest_fetch_kib": 2064867.0, "finest_write_kib": 1572872.5},
     },
 }
 
